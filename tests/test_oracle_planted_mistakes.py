@@ -1,0 +1,78 @@
+"""Plausible mistakes planted in the CPU oracle must fail at least one pin.
+
+Each case monkeypatches one oracle routine with a wrong variant (a dropped
+factor, transposed axes, a wrong sign or step) and runs the fast pins that
+should catch it.  Nothing here touches a GPU.
+"""
+import numpy as np
+import pytest
+import scipy.fft as sfft
+
+from tests import test_oracle_pins as pins  # noqa: E402
+from oracle import mpe
+
+
+def _fails(fn, *args):
+    try:
+        fn(*args)
+    except AssertionError:
+        return True
+    return False
+
+
+def _ks_no_half(grid, box, hbar2_over_m=1.0):
+    return 2.0 * _REAL_KS(grid, box, hbar2_over_m)
+
+
+def _ks_axes_swapped(grid, box, hbar2_over_m=1.0):
+    nx, ny, nz = grid
+    Lx, Ly, Lz = box
+    qx = 2 * np.pi * sfft.rfftfreq(nx, d=Lz / nx)      # wrong box length on x
+    qy = 2 * np.pi * sfft.fftfreq(ny, d=Ly / ny)
+    qz = 2 * np.pi * sfft.fftfreq(nz, d=Lx / nz)
+    return 0.5 * hbar2_over_m * (qz[:, None, None] ** 2 + qy[None, :, None] ** 2 + qx[None, None, :] ** 2)
+
+
+_REAL_KS = mpe.kinetic_symbol
+_REAL_COEF = mpe.mpe_coefficients_exact
+_REAL_T2 = mpe.t2
+
+
+def _coef_sign(K):
+    c = _REAL_COEF(K)
+    return [-x if i == 0 else x for i, x in enumerate(c)] if K > 1 else c
+
+
+def _t2_full_v(psi, V, tau, grid, box, hbar2_over_m=1.0, _ksym=None):
+    return _REAL_T2(psi, 2.0 * V, tau, grid, box, hbar2_over_m, _ksym)
+
+
+def _mpe_wrong_substep(psi, V, dt, K, grid, box, hbar2_over_m=1.0):
+    c = mpe.mpe_coefficients(K)
+    acc = np.zeros_like(psi)
+    for k in range(1, K + 1):
+        u = psi
+        for _ in range(k):
+            u = _REAL_T2(u, V, dt / (k * k), grid, box, hbar2_over_m)    # dt/k^2 instead of dt/k
+        acc += c[k - 1] * u
+    return acc
+
+
+CASES = [
+    ("kinetic symbol without the 1/2", "kinetic_symbol", _ks_no_half,
+     [(pins.test_h_apply_matches_dense, ((8, 8, 8), (8.0, 8.0, 8.0)))]),
+    ("kinetic symbol with box lengths of x and z exchanged", "kinetic_symbol", _ks_axes_swapped,
+     [(pins.test_h_apply_matches_dense, ((8, 6, 4), (7.0, 5.0, 9.0)))]),
+    ("first coefficient with the wrong sign", "mpe_coefficients_exact", _coef_sign,
+     [(pins.test_coefficients_match_printed_fractions, ()), (pins.test_coefficients_are_richardson_weights, (3,))]),
+    ("full potential on both sides of T2", "t2", _t2_full_v,
+     [(pins.test_t2_matches_dense, ((8, 8, 8), (8.0, 8.0, 8.0), 0.4))]),
+    ("sub-step dt/k^2 in the expansion", "mpe_apply", _mpe_wrong_substep,
+     [(pins.test_mpe_apply_matches_dense_expansion, (2,))]),
+]
+
+
+@pytest.mark.parametrize("name,attr,wrong,checks", CASES, ids=[c[0] for c in CASES])
+def test_planted_mistake_is_caught(monkeypatch, name, attr, wrong, checks):
+    monkeypatch.setattr(mpe, attr, wrong)
+    assert any(_fails(fn, *args) for fn, args in checks), name
