@@ -1,0 +1,90 @@
+"""ctypes binding of libmpe.so (argument marshalling only).
+
+Every entry point of ``include/mpe.h`` is declared here with the same name.
+The library is loaded from this package directory; if it is missing the
+import fails loudly -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpe.so")
+
+MPE_OK = 0
+STATUS = {
+    0: "MPE_OK", 1: "MPE_ERR_INVALID_ARGUMENT", 2: "MPE_ERR_UNSUPPORTED", 3: "MPE_ERR_OUT_OF_MEMORY",
+    4: "MPE_ERR_NOT_POSITIVE_DEFINITE", 5: "MPE_ERR_EIG_NO_CONVERGENCE", 6: "MPE_ERR_NONFINITE",
+    7: "MPE_ERR_DEVICE", 8: "MPE_ERR_STATE",
+}
+MPE_FP64, MPE_FP32 = 0, 1
+KERNEL_CLASSES = ["plane_fwd", "pencil", "plane_link", "plane_tail", "h_apply", "gram", "small_dense",
+                  "rotate", "other"]
+
+_dp = C.POINTER(C.c_double)
+_vp = C.c_void_p
+_i32 = C.c_int32
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "mpe_abi_version": (C.c_int, []),
+    "mpe_status_string": (C.c_char_p, [C.c_int]),
+    "mpe_coefficients": (C.c_int, [_i32, _dp]),
+    "mpe_plan_create": (C.c_int, [C.POINTER(_vp), C.POINTER(_i32), _dp, _i32, _i32, C.c_int, _i32, _vp]),
+    "mpe_plan_destroy": (C.c_int, [_vp]),
+    "mpe_last_error": (C.c_char_p, [_vp]),
+    "mpe_workspace_bytes": (C.c_int64, [_vp]),
+    "mpe_set_potential": (C.c_int, [_vp, _vp, C.c_double]),
+    "mpe_step": (C.c_int, [_vp, _vp, C.c_double]),
+    "mpe_apply_h": (C.c_int, [_vp, _vp, _vp]),
+    "mpe_orthonormalize": (C.c_int, [_vp, _vp]),
+    "mpe_rayleigh_ritz": (C.c_int, [_vp, _vp, _dp]),
+    "mpe_residuals": (C.c_int, [_vp, _vp, _dp, _dp, _dp]),
+    "mpe_iterate": (C.c_int, [_vp, _vp, C.c_double, _dp, _dp, _dp, _dp]),
+    "mpe_set_states_per_launch": (C.c_int, [_vp, _i32]),
+    "mpe_profile_enable": (C.c_int, [_vp, _i32]),
+    "mpe_get_kernel_times": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64)]),
+}
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libmpe.so not found at {path}; build it with `python -m paper_0809_3739_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB
+
+
+class MpeError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        self.code = code
+        self.name = STATUS.get(code, f"status {code}")
+        super().__init__(f"{self.name}: {msg}" if msg else self.name)
+
+
+def check(code: int, plan=None) -> None:
+    if code != MPE_OK:
+        msg = lib().mpe_last_error(plan).decode() if plan else ""
+        raise MpeError(code, msg)
+
+
+def coefficients(order: int):
+    """c_1..c_K of the order-2K expansion, computed by the library."""
+    K = order // 2
+    buf = (C.c_double * max(K, 1))()
+    check(lib().mpe_coefficients(order, buf))
+    return [buf[i] for i in range(K)]

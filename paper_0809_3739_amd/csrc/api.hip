@@ -1,0 +1,869 @@
+// C ABI of libmpe: plan management and the launch sequences of one
+// multi-product step, the H application, orthonormalisation, Rayleigh-Ritz,
+// the variances and the fused iteration.  See include/mpe.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpe.h"
+#include "la.hpp"
+#include "prop.hpp"
+
+using namespace mpe;
+
+namespace {
+
+// ------------------------------------------------------------------ device table kernels
+// fac[j][p] = exp(-dt V[p] / (j + 1)), j = 0..ntab-1: the potential half- and
+// full-steps exp(-tau V/2) and exp(-tau V) of every chain (tau = dt/k).
+template <typename F>
+__global__ void factor_tables_kernel(const double* __restrict__ V, long N, double dt, int ntab, F* __restrict__ out) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double v = V[p];
+  for (int j = 0; j < ntab; ++j) out[(long)j * N + p] = (F)exp(-dt * v / (double)(j + 1));
+}
+
+template <typename F>
+__global__ void cast_kernel(const double* __restrict__ in, long n, F* __restrict__ out) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) out[p] = (F)in[p];
+}
+
+__device__ __forceinline__ double wavenumber(int k, int n, double L) {
+  const int mfreq = (k <= n / 2) ? k : k - n;
+  return 2.0 * 3.14159265358979323846 * (double)mfreq / L;
+}
+
+// Per-axis kinetic tables on the half spectrum.  For chain k (tau = dt/k):
+//   ex[kx] = exp(-tau hbar^2/2m qx^2), ey, ez likewise, ez also carrying 1/(nx ny nz)
+// (the three unnormalised inverse transforms); and the additive tables of T itself:
+//   hx[kx] = hbar^2/2m qx^2 / (nx ny nz), ...
+template <typename F>
+__global__ void kinetic_tables_kernel(int nx, int ny, int nz, double Lx, double Ly, double Lz, double h2m, double dt,
+                                      int K, F* __restrict__ exp_tab, F* __restrict__ add_tab) {
+  const int nxh = nx / 2 + 1, len = nxh + ny + nz;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  const double inv_n = 1.0 / ((double)nx * ny * nz);
+  double q;
+  bool is_z = false;
+  if (i < nxh) q = wavenumber(i, nx, Lx);
+  else if (i < nxh + ny) q = wavenumber(i - nxh, ny, Ly);
+  else { q = wavenumber(i - nxh - ny, nz, Lz); is_z = true; }
+  const double t = 0.5 * h2m * q * q;
+  for (int k = 1; k <= K; ++k) {
+    double e = exp(-(dt / k) * t);
+    if (is_z) e *= inv_n;
+    exp_tab[(long)(k - 1) * len + i] = (F)e;
+  }
+  add_tab[i] = (F)(t * inv_n);
+}
+
+// R^H partials for a block with given values: part[c][j] = sum over chunk c of (hpsi - e_j psi)^2
+template <typename F>
+__global__ __launch_bounds__(256) void residual_kernel(const F* __restrict__ psi, const F* __restrict__ hpsi,
+                                                       const double* __restrict__ eig, long N, long chunk, int mp,
+                                                       double* __restrict__ part) {
+  const int j = blockIdx.y;
+  const long b = (long)blockIdx.x * chunk, e = min(N, b + chunk);
+  const double ej = eig[j];
+  double s = 0.0;
+  for (long p = b + threadIdx.x; p < e; p += 256) {
+    const double d = (double)hpsi[(long)j * N + p] - ej * (double)psi[(long)j * N + p];
+    s += d * d;
+  }
+  __shared__ double red[4];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(long)blockIdx.x * mp + j] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ------------------------------------------------------------------ host-side exact coefficients
+long long gcdll(long long a, long long b) {
+  a = a < 0 ? -a : a;
+  b = b < 0 ? -b : b;
+  while (b) { long long t = a % b; a = b; b = t; }
+  return a;
+}
+
+// c_i = prod_{j != i} i^2/(i^2 - j^2) as a reduced fraction, then rounded once.
+bool mpe_coeffs(int K, double* c) {
+  if (K < 1 || K > MAX_K) return false;
+  for (int i = 1; i <= K; ++i) {
+    long long num = 1, den = 1;
+    for (int j = 1; j <= K; ++j) {
+      if (j == i) continue;
+      num *= (long long)i * i;
+      den *= (long long)i * i - (long long)j * j;
+      const long long g = gcdll(num, den);
+      num /= g;
+      den /= g;
+    }
+    if (den < 0) { den = -den; num = -num; }
+    c[i - 1] = (double)num / (double)den;   // num, den < 2^53: one rounding
+  }
+  return true;
+}
+
+struct Timer {
+  hipEvent_t a, b;
+  int kc;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ the plan
+struct mpe_plan_s {
+  int nx = 0, ny = 0, nz = 0, nxh = 0;
+  double Lx = 0, Ly = 0, Lz = 0;
+  int n = 0, g = 0, m = 0, mp = 0, K = 0, dbl = 0;
+  long N = 0, M = 0, spec = 0;            // points, columns per z, spectrum elements per state
+  size_t fsz = 0;                         // sizeof data type
+  hipStream_t st = nullptr;
+  std::string err;
+
+  // workspace
+  void* W = nullptr;           // K chains x m states x spec complex
+  void* phi = nullptr;         // m x N
+  void* hphi = nullptr;        // m x N
+  double* V64 = nullptr;       // N
+  void* Vf = nullptr;          // N, data type
+  void* fac = nullptr;         // 2K x N
+  void* kin = nullptr;         // K x (nxh+ny+nz)
+  void* hk = nullptr;          // nxh+ny+nz
+  void* roots = nullptr;       // rx | ry | rz | wpost
+  size_t off_ry = 0, off_rz = 0, off_wp = 0;
+  double* partials = nullptr;  // gram / residual partials
+  size_t partials_bytes = 0;
+  double* mats = nullptr;      // S, Hs, M, L, C (mp x mp each)
+  double* rot = nullptr;       // Jacobi rotation log
+  size_t rot_count = 0;
+  double* res = nullptr;       // theta | rh | re | re_perp (MAXM each) | scratch (2 MAXM) | status
+  int* status = nullptr;
+  double* host_res = nullptr;  // pinned mirror of res + status
+  size_t res_bytes = 0;
+  int64_t ws_bytes = 0;
+
+  bool have_v = false;
+  double h2m = 1.0;
+  double tab_dt = -1.0;
+  double last_dt = -1.0;
+  int states_per_launch = 0;
+  int max_sweeps = 60;
+  double jacobi_tol = 1e-14;
+  double pivot_tol = 1e-13;
+  const void* rr_cache_psi = nullptr;   // H psi cached in hphi for this psi
+
+  // timing
+  bool prof = false;
+  std::vector<Timer> timers;
+  std::vector<hipEvent_t> pool;
+  double kms[MPE_KC_COUNT] = {0};
+  int64_t kcount[MPE_KC_COUNT] = {0};
+
+  double* S() { return mats; }
+  double* Hs() { return mats + (size_t)mp * mp; }
+  double* Mm() { return mats + 2 * (size_t)mp * mp; }
+  double* L() { return mats + 3 * (size_t)mp * mp; }
+  double* C() { return mats + 4 * (size_t)mp * mp; }
+  double* theta() { return res; }
+  double* rh() { return res + MAXM; }
+  double* re() { return res + 2 * MAXM; }
+  double* reperp() { return res + 3 * MAXM; }
+  double* scratch() { return res + 4 * MAXM; }
+  const void* rx() const { return roots; }
+  const void* ry() const { return (const char*)roots + off_ry; }
+  const void* rz() const { return (const char*)roots + off_rz; }
+  const void* wpost() const { return (const char*)roots + off_wp; }
+  size_t cx_size() const { return 2 * fsz; }
+};
+
+namespace {
+
+mpe_status fail(mpe_plan p, mpe_status s, const std::string& msg) {
+  if (p) p->err = msg;
+  return s;
+}
+
+#define HIPCHK(p, expr)                                                                           \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return fail(p, MPE_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+hipEvent_t get_event(mpe_plan p) {
+  if (!p->pool.empty()) {
+    hipEvent_t e = p->pool.back();
+    p->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void tic(mpe_plan p, Timer& t, int kc) {
+  t.kc = kc;
+  t.a = t.b = nullptr;
+  if (!p->prof) return;
+  t.a = get_event(p);
+  t.b = get_event(p);
+  if (t.a) (void)hipEventRecord(t.a, p->st);
+}
+
+void toc(mpe_plan p, Timer& t) {
+  if (!p->prof || !t.a || !t.b) return;
+  (void)hipEventRecord(t.b, p->st);
+  p->timers.push_back(t);
+}
+
+void collect_times(mpe_plan p) {
+  if (p->timers.empty()) return;
+  (void)hipStreamSynchronize(p->st);
+  for (auto& t : p->timers) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      p->kms[t.kc] += ms;
+      p->kcount[t.kc] += 1;
+    }
+    p->pool.push_back(t.a);
+    p->pool.push_back(t.b);
+  }
+  p->timers.clear();
+}
+
+template <typename F>
+hipError_t launch_factor_tables(mpe_plan p, double dt) {
+  const long N = p->N;
+  hipLaunchKernelGGL(factor_tables_kernel<F>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, p->st, p->V64, N, dt,
+                     2 * p->K, reinterpret_cast<F*>(p->fac));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int len = p->nxh + p->ny + p->nz;
+  hipLaunchKernelGGL(kinetic_tables_kernel<F>, dim3((len + 255) / 256), dim3(256), 0, p->st, p->nx, p->ny, p->nz, p->Lx,
+                     p->Ly, p->Lz, p->h2m, dt, p->K, reinterpret_cast<F*>(p->kin), reinterpret_cast<F*>(p->hk));
+  return hipGetLastError();
+}
+
+mpe_status ensure_tables(mpe_plan p, double dt) {
+  if (!p->have_v) return fail(p, MPE_ERR_STATE, "no potential set (mpe_set_potential)");
+  if (p->tab_dt == dt) return MPE_OK;
+  HIPCHK(p, p->dbl ? launch_factor_tables<double>(p, dt) : launch_factor_tables<float>(p, dt));
+  p->tab_dt = dt;
+  return MPE_OK;
+}
+
+// Launch groups of states: [s0, s0 + count) with count <= states_per_launch.
+template <typename Fn>
+hipError_t for_groups(mpe_plan p, Fn fn) {
+  const int G = (p->states_per_launch > 0 && p->states_per_launch < p->m) ? p->states_per_launch : p->m;
+  for (int s0 = 0; s0 < p->m; s0 += G) {
+    hipError_t e = fn(s0, std::min(G, p->m - s0));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+PlaneArgs plane_base(mpe_plan p) {
+  PlaneArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.rx = p->rx();
+  a.ry = p->ry();
+  a.wpost = p->wpost();
+  a.real_state_stride = p->N;
+  a.spec_state_stride = p->spec;
+  return a;
+}
+
+PencilArgs pencil_base(mpe_plan p, void* data, const void* tab) {
+  PencilArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.data = data;
+  a.rz = p->rz();
+  const size_t f = p->fsz;
+  a.tx = tab;
+  a.ty = (const char*)tab + f * p->nxh;
+  a.tz = (const char*)tab + f * (p->nxh + p->ny);
+  a.state_stride = p->spec;
+  a.M = (int)p->M;
+  a.NXH = p->nxh;
+  return a;
+}
+
+void* chain_spec(mpe_plan p, int k) {  // k = 0..K-1
+  return (char*)p->W + (size_t)k * p->m * p->spec * p->cx_size();
+}
+
+// dst <- T_2K(dt) src, all m states (src may equal dst).
+mpe_status run_step(mpe_plan p, const void* src, void* dst, double dt) {
+  mpe_status s = ensure_tables(p, dt);
+  if (s != MPE_OK) return s;
+  const size_t f = p->fsz;
+  double c[MAX_K];
+  mpe_coeffs(p->K, c);
+  for (int k = 1; k <= p->K; ++k) {
+    void* Wk = chain_spec(p, k - 1);
+    const void* half = (const char*)p->fac + (size_t)(2 * k - 1) * p->N * f;  // exp(-dt V / 2k)
+    const void* full = (const char*)p->fac + (size_t)(k - 1) * p->N * f;      // exp(-dt V / k)
+    const void* ktab = (const char*)p->kin + (size_t)(k - 1) * (p->nxh + p->ny + p->nz) * f;
+    Timer t;
+    tic(p, t, MPE_KC_PLANE_FWD);
+    HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
+             PlaneArgs a = plane_base(p);
+             a.real_in = src;
+             a.fac = half;
+             a.spec_out = Wk;
+             a.state0 = s0;
+             return launch_plane(p->dbl, PM_FWD, p->nx, a, p->nz, cnt, p->st);
+           }));
+    toc(p, t);
+    for (int l = 1; l <= k; ++l) {
+      tic(p, t, MPE_KC_PENCIL);
+      HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
+               PencilArgs a = pencil_base(p, Wk, ktab);
+               a.state0 = s0;
+               return launch_pencil(p->dbl, PK_EXP, p->nz, a, cnt, p->st);
+             }));
+      toc(p, t);
+      if (l < k) {
+        tic(p, t, MPE_KC_PLANE_LINK);
+        HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
+                 PlaneArgs a = plane_base(p);
+                 a.spec_in = Wk;
+                 a.spec_out = Wk;
+                 a.fac = full;
+                 a.state0 = s0;
+                 return launch_plane(p->dbl, PM_LINK, p->nx, a, p->nz, cnt, p->st);
+               }));
+        toc(p, t);
+      }
+    }
+  }
+  Timer t;
+  tic(p, t, MPE_KC_PLANE_TAIL);
+  HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
+           PlaneArgs a = plane_base(p);
+           a.spec_in = chain_spec(p, 0);
+           a.chain_stride = (long)p->m * p->spec;
+           a.fac = p->fac;
+           a.fac_table_stride = p->N;
+           a.real_out = dst;
+           a.K = p->K;
+           for (int k = 0; k < p->K; ++k) a.coef[k] = c[k];
+           a.state0 = s0;
+           return launch_plane(p->dbl, PM_TAIL, p->nx, a, p->nz, cnt, p->st);
+         }));
+  toc(p, t);
+  p->last_dt = dt;
+  return MPE_OK;
+}
+
+// hdst <- H src (src != hdst); uses chain 0's spectrum buffer as scratch.
+mpe_status run_h(mpe_plan p, const void* src, void* hdst) {
+  if (!p->have_v) return fail(p, MPE_ERR_STATE, "no potential set (mpe_set_potential)");
+  if (p->tab_dt < 0) {
+    mpe_status s = ensure_tables(p, 1.0);  // builds the additive table (independent of dt)
+    if (s != MPE_OK) return s;
+  }
+  void* Wh = chain_spec(p, 0);
+  Timer t;
+  tic(p, t, MPE_KC_H_APPLY);
+  HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
+           PlaneArgs a = plane_base(p);
+           a.real_in = src;
+           a.fac = nullptr;
+           a.spec_out = Wh;
+           a.state0 = s0;
+           hipError_t e = launch_plane(p->dbl, PM_FWD, p->nx, a, p->nz, cnt, p->st);
+           if (e != hipSuccess) return e;
+           PencilArgs b = pencil_base(p, Wh, p->hk);
+           b.state0 = s0;
+           e = launch_pencil(p->dbl, PK_ADD, p->nz, b, cnt, p->st);
+           if (e != hipSuccess) return e;
+           PlaneArgs c = plane_base(p);
+           c.spec_in = Wh;
+           c.real_in = src;
+           c.fac = p->Vf;
+           c.real_out = hdst;
+           c.state0 = s0;
+           return launch_plane(p->dbl, PM_HTAIL, p->nx, c, p->nz, cnt, p->st);
+         }));
+  toc(p, t);
+  return MPE_OK;
+}
+
+int gram_chunks(mpe_plan p, long* chunk) {
+  long nch = std::min<long>(256, std::max<long>(1, (p->N + 4095) / 4096));
+  long c = (p->N + nch - 1) / nch;
+  c = (c + 15) / 16 * 16;
+  nch = (p->N + c - 1) / c;
+  *chunk = c;
+  return (int)nch;
+}
+
+int rot_chunks(mpe_plan p, long* chunk) {
+  long nch = std::min<long>(1024, std::max<long>(1, (p->N + 255) / 256));
+  long c = (p->N + nch - 1) / nch;
+  c = (c + 63) / 64 * 64;
+  nch = (p->N + c - 1) / c;
+  *chunk = c;
+  return (int)nch;
+}
+
+// Overlaps X_i Y_i^T (i < nprod) reduced into outs[i] (mp x mp float64 each, contiguous from out0).
+mpe_status run_gram(mpe_plan p, const void* const* X, const void* const* Y, int nprod, double* out0) {
+  GramArgs g;
+  std::memset(&g, 0, sizeof(g));
+  for (int i = 0; i < nprod; ++i) {
+    g.X[i] = X[i];
+    g.Y[i] = Y[i];
+  }
+  long chunk;
+  const int nch = gram_chunks(p, &chunk);
+  g.partials = p->partials;
+  g.N = p->N;
+  g.chunk = chunk;
+  g.m = p->m;
+  g.mp = p->mp;
+  Timer t;
+  tic(p, t, MPE_KC_GRAM);
+  HIPCHK(p, launch_gram(p->dbl, g, nprod, nch, p->st));
+  HIPCHK(p, launch_reduce(p->partials, nch, (long)p->mp * p->mp, nprod, out0, p->st));
+  toc(p, t);
+  return MPE_OK;
+}
+
+mpe_status run_small_dense(mpe_plan p, int mode) {
+  SmallDenseArgs d;
+  std::memset(&d, 0, sizeof(d));
+  d.S = p->S();
+  d.Hs = p->Hs();
+  d.L = p->L();
+  d.rot = p->rot;
+  d.scratch = p->scratch();
+  d.C = p->C();
+  d.theta = p->theta();
+  d.status = p->status;
+  d.m = p->m;
+  d.mp = p->mp;
+  d.mode = mode;
+  d.max_sweeps = p->max_sweeps;
+  d.tol = p->jacobi_tol;
+  d.pivot_tol = p->pivot_tol;
+  Timer t;
+  tic(p, t, MPE_KC_SMALL_DENSE);
+  HIPCHK(p, launch_small_dense(d, p->st));
+  toc(p, t);
+  return MPE_OK;
+}
+
+mpe_status run_rotate(mpe_plan p, const void* Phi, const void* HPhi, void* Psi, void* HPsi) {
+  RotateArgs r;
+  std::memset(&r, 0, sizeof(r));
+  long chunk;
+  const int nch = rot_chunks(p, &chunk);
+  r.Phi = Phi;
+  r.HPhi = HPhi;
+  r.C = p->C();
+  r.theta = p->theta();
+  r.Psi = Psi;
+  r.HPsi = HPsi;
+  r.res_partials = p->partials;
+  r.status = p->status;
+  r.N = p->N;
+  r.chunk = chunk;
+  r.m = p->m;
+  r.mp = p->mp;
+  Timer t;
+  tic(p, t, MPE_KC_ROTATE);
+  HIPCHK(p, launch_rotate(p->dbl, HPhi != nullptr, r, nch, p->st));
+  if (HPhi) HIPCHK(p, launch_reduce(p->partials, nch, (long)p->mp, 1, p->rh(), p->st));
+  toc(p, t);
+  return MPE_OK;
+}
+
+// Copy results + status to the pinned mirror and wait.
+mpe_status fetch(mpe_plan p) {
+  HIPCHK(p, hipMemcpyAsync(p->host_res, p->res, p->res_bytes, hipMemcpyDeviceToHost, p->st));
+  HIPCHK(p, hipStreamSynchronize(p->st));
+  collect_times(p);
+  return MPE_OK;
+}
+
+mpe_status status_to_error(mpe_plan p) {
+  const int* hs = reinterpret_cast<const int*>(p->host_res + 6 * MAXM);
+  switch (hs[0]) {
+    case ST_OK: return MPE_OK;
+    case ST_NOT_SPD: {
+      char b[128];
+      snprintf(b, sizeof b, "overlap matrix not positive definite at pivot %d", hs[1]);
+      return fail(p, MPE_ERR_NOT_POSITIVE_DEFINITE, b);
+    }
+    case ST_NONFINITE: {
+      char b[128];
+      snprintf(b, sizeof b, "non-finite value in the overlap matrix at pivot %d", hs[1]);
+      return fail(p, MPE_ERR_NONFINITE, b);
+    }
+    case ST_EIG_NO_CONV: {
+      char b[128];
+      snprintf(b, sizeof b, "Jacobi eigensolver did not converge in %d sweeps", hs[1]);
+      return fail(p, MPE_ERR_EIG_NO_CONVERGENCE, b);
+    }
+    default: return fail(p, MPE_ERR_DEVICE, "unknown device status");
+  }
+}
+
+void copy_out(double* dst, const double* src, int m) {
+  if (dst) std::memcpy(dst, src, sizeof(double) * m);
+}
+
+bool size_ok(int n) {
+  switch (n) {
+    case 8: case 16: case 32: case 48: case 64: case 96: case 128: case 192: return true;
+    default: return false;
+  }
+}
+
+void host_roots(int L, std::vector<double>& out) {
+  for (int j = 0; j < L; ++j) {
+    const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)L;
+    out.push_back((double)cosl(ang));
+    out.push_back((double)sinl(ang));
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ exported API
+extern "C" {
+
+int mpe_abi_version(void) { return MPE_ABI_VERSION; }
+
+const char* mpe_status_string(mpe_status s) {
+  switch (s) {
+    case MPE_OK: return "ok";
+    case MPE_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case MPE_ERR_UNSUPPORTED: return "unsupported configuration";
+    case MPE_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case MPE_ERR_NOT_POSITIVE_DEFINITE: return "overlap matrix not positive definite";
+    case MPE_ERR_EIG_NO_CONVERGENCE: return "eigensolver did not converge";
+    case MPE_ERR_NONFINITE: return "non-finite values";
+    case MPE_ERR_DEVICE: return "HIP runtime error";
+    case MPE_ERR_STATE: return "invalid call order";
+  }
+  return "unknown status";
+}
+
+mpe_status mpe_coefficients(int32_t order, double* c) {
+  if (!c || order < 2 || order > 2 * MAX_K || order % 2) return MPE_ERR_INVALID_ARGUMENT;
+  return mpe_coeffs(order / 2, c) ? MPE_OK : MPE_ERR_INVALID_ARGUMENT;
+}
+
+mpe_status mpe_plan_destroy(mpe_plan p) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  (void)hipStreamSynchronize(p->st);
+  for (auto& t : p->timers) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (auto e : p->pool) (void)hipEventDestroy(e);
+  void* bufs[] = {p->W, p->phi, p->hphi, p->V64, p->Vf, p->fac, p->kin, p->hk, p->roots,
+                  p->partials, p->mats, p->rot, p->res};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (p->host_res) (void)hipHostFree(p->host_res);
+  delete p;
+  return MPE_OK;
+}
+
+mpe_status mpe_plan_create(mpe_plan* out, const int32_t grid[3], const double box[3], int32_t n_states, int32_t order,
+                           mpe_precision prec, int32_t n_guard, void* hip_stream) {
+  if (!out) return MPE_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (!grid || !box) return MPE_ERR_INVALID_ARGUMENT;
+  if (order < 2 || order > 2 * MAX_K || order % 2) return MPE_ERR_INVALID_ARGUMENT;
+  if (prec != MPE_FP64 && prec != MPE_FP32) return MPE_ERR_INVALID_ARGUMENT;
+  if (n_states < 1 || n_guard < 0) return MPE_ERR_INVALID_ARGUMENT;
+  for (int i = 0; i < 3; ++i) {
+    if (grid[i] < 2 || grid[i] % 2) return MPE_ERR_INVALID_ARGUMENT;
+    if (!(box[i] > 0.0) || !std::isfinite(box[i])) return MPE_ERR_INVALID_ARGUMENT;
+  }
+  const long N = (long)grid[0] * grid[1] * grid[2];
+  const int m = n_states + n_guard;
+  if (m > N) return MPE_ERR_INVALID_ARGUMENT;
+  if (m > MAXM) return MPE_ERR_UNSUPPORTED;
+  if (!size_ok(grid[0]) || !size_ok(grid[1]) || !size_ok(grid[2])) return MPE_ERR_UNSUPPORTED;
+  if (!plane_supported(prec == MPE_FP64, grid[0], grid[1]) || !pencil_supported(grid[2])) return MPE_ERR_UNSUPPORTED;
+
+  mpe_plan p = new mpe_plan_s();
+  p->nx = grid[0];
+  p->ny = grid[1];
+  p->nz = grid[2];
+  p->nxh = p->nx / 2 + 1;
+  p->Lx = box[0];
+  p->Ly = box[1];
+  p->Lz = box[2];
+  p->n = n_states;
+  p->g = n_guard;
+  p->m = m;
+  p->mp = (m + 15) / 16 * 16;
+  p->K = order / 2;
+  p->dbl = prec == MPE_FP64;
+  p->N = N;
+  p->M = (long)p->ny * p->nxh;
+  p->spec = (long)p->nz * p->M;
+  p->fsz = p->dbl ? sizeof(double) : sizeof(float);
+  p->st = reinterpret_cast<hipStream_t>(hip_stream);
+
+  auto alloc = [&](void** ptr, size_t bytes) -> bool {
+    if (hipMalloc(ptr, bytes) != hipSuccess) {
+      *ptr = nullptr;
+      return false;
+    }
+    p->ws_bytes += (int64_t)bytes;
+    return true;
+  };
+  const size_t f = p->fsz, cxs = 2 * f;
+  long gch;
+  const int ngch = gram_chunks(p, &gch);
+  long rch;
+  const int nrch = rot_chunks(p, &rch);
+  p->partials_bytes = std::max((size_t)3 * ngch * p->mp * p->mp, (size_t)nrch * p->mp) * sizeof(double);
+  const int nn = (m + 1) & ~1;
+  p->rot_count = (size_t)(p->max_sweeps + 1) * (nn - 1) * (nn / 2) + 16;
+  p->res_bytes = 6 * MAXM * sizeof(double) + 4 * sizeof(int);
+  const int tablen = p->nxh + p->ny + p->nz;
+  std::vector<double> r;
+  host_roots(p->nx / 2, r);
+  p->off_ry = r.size() / 2 * cxs;
+  host_roots(p->ny, r);
+  p->off_rz = r.size() / 2 * cxs;
+  host_roots(p->nz, r);
+  p->off_wp = r.size() / 2 * cxs;
+  {
+    std::vector<double> w;
+    host_roots(p->nx, w);
+    for (int k = 0; k <= p->nx / 4; ++k) {
+      r.push_back(w[2 * k]);
+      r.push_back(w[2 * k + 1]);
+    }
+  }
+  bool ok = alloc(&p->W, (size_t)p->K * m * p->spec * cxs) && alloc(&p->phi, (size_t)m * N * f) &&
+            alloc(&p->hphi, (size_t)m * N * f) && alloc((void**)&p->V64, N * sizeof(double)) &&
+            alloc(&p->Vf, N * f) && alloc(&p->fac, (size_t)2 * p->K * N * f) &&
+            alloc(&p->kin, (size_t)p->K * tablen * f) && alloc(&p->hk, (size_t)tablen * f) &&
+            alloc(&p->roots, r.size() / 2 * cxs) && alloc((void**)&p->partials, p->partials_bytes) &&
+            alloc((void**)&p->mats, 5 * (size_t)p->mp * p->mp * sizeof(double)) &&
+            alloc((void**)&p->rot, p->rot_count * 4 * sizeof(double)) && alloc((void**)&p->res, p->res_bytes);
+  if (!ok) {
+    mpe_plan_destroy(p);
+    return MPE_ERR_OUT_OF_MEMORY;
+  }
+  p->status = reinterpret_cast<int*>(p->res + 6 * MAXM);
+  if (hipHostMalloc((void**)&p->host_res, p->res_bytes, hipHostMallocDefault) != hipSuccess) {
+    mpe_plan_destroy(p);
+    return MPE_ERR_OUT_OF_MEMORY;
+  }
+  // roots in the data type
+  hipError_t e;
+  if (p->dbl) {
+    e = hipMemcpyAsync(p->roots, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice, p->st);
+  } else {
+    std::vector<float> rf(r.begin(), r.end());
+    e = hipMemcpyAsync(p->roots, rf.data(), rf.size() * sizeof(float), hipMemcpyHostToDevice, p->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->st);
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(p->res, 0, p->res_bytes, p->st);
+  if (e == hipSuccess) e = hipMemsetAsync(p->mats, 0, 5 * (size_t)p->mp * p->mp * sizeof(double), p->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->st);
+  if (e != hipSuccess) {
+    mpe_plan_destroy(p);
+    return MPE_ERR_DEVICE;
+  }
+  *out = p;
+  return MPE_OK;
+}
+
+const char* mpe_last_error(mpe_plan p) { return p ? p->err.c_str() : "null plan"; }
+
+int64_t mpe_workspace_bytes(mpe_plan p) { return p ? p->ws_bytes : 0; }
+
+mpe_status mpe_set_potential(mpe_plan p, const double* V, double hbar2_over_m) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (!V) return fail(p, MPE_ERR_INVALID_ARGUMENT, "V is null");
+  if (!(hbar2_over_m > 0.0) || !std::isfinite(hbar2_over_m))
+    return fail(p, MPE_ERR_INVALID_ARGUMENT, "hbar2_over_m must be positive");
+  HIPCHK(p, hipMemcpyAsync(p->V64, V, p->N * sizeof(double), hipMemcpyDeviceToDevice, p->st));
+  const unsigned nb = (unsigned)((p->N + 255) / 256);
+  if (p->dbl)
+    hipLaunchKernelGGL(cast_kernel<double>, dim3(nb), dim3(256), 0, p->st, p->V64, p->N, (double*)p->Vf);
+  else
+    hipLaunchKernelGGL(cast_kernel<float>, dim3(nb), dim3(256), 0, p->st, p->V64, p->N, (float*)p->Vf);
+  HIPCHK(p, hipGetLastError());
+  p->h2m = hbar2_over_m;
+  p->have_v = true;
+  p->tab_dt = -1.0;
+  p->rr_cache_psi = nullptr;
+  return MPE_OK;
+}
+
+mpe_status mpe_step(mpe_plan p, void* psi, double dt) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (!psi) return fail(p, MPE_ERR_INVALID_ARGUMENT, "psi is null");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, MPE_ERR_INVALID_ARGUMENT, "dt must be positive");
+  p->rr_cache_psi = nullptr;
+  mpe_status s = run_step(p, psi, psi, dt);
+  collect_times(p);
+  return s;
+}
+
+mpe_status mpe_apply_h(mpe_plan p, const void* psi, void* hpsi) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (!psi || !hpsi) return fail(p, MPE_ERR_INVALID_ARGUMENT, "null array");
+  if (psi == hpsi) return fail(p, MPE_ERR_INVALID_ARGUMENT, "psi and hpsi must differ");
+  p->rr_cache_psi = nullptr;
+  mpe_status s = run_h(p, psi, hpsi);
+  collect_times(p);
+  return s;
+}
+
+mpe_status mpe_orthonormalize(mpe_plan p, void* psi) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (!psi) return fail(p, MPE_ERR_INVALID_ARGUMENT, "psi is null");
+  p->rr_cache_psi = nullptr;
+  const void* X[1] = {psi};
+  mpe_status s = run_gram(p, X, X, 1, p->S());
+  if (s == MPE_OK) s = run_small_dense(p, SD_ORTHO);
+  if (s == MPE_OK) s = run_rotate(p, psi, nullptr, psi, nullptr);
+  if (s != MPE_OK) return s;
+  s = fetch(p);
+  if (s != MPE_OK) return s;
+  return status_to_error(p);
+}
+
+mpe_status mpe_rayleigh_ritz(mpe_plan p, void* psi, double* eig) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (!psi || !eig) return fail(p, MPE_ERR_INVALID_ARGUMENT, "null array");
+  p->rr_cache_psi = nullptr;
+  mpe_status s = run_h(p, psi, p->hphi);
+  const void* X[2] = {psi, psi};
+  const void* Y[2] = {psi, p->hphi};
+  if (s == MPE_OK) s = run_gram(p, X, Y, 2, p->S());
+  if (s == MPE_OK) s = run_small_dense(p, SD_RR);
+  if (s == MPE_OK) s = run_rotate(p, psi, p->hphi, psi, p->hphi);
+  if (s != MPE_OK) return s;
+  s = fetch(p);
+  if (s != MPE_OK) return s;
+  s = status_to_error(p);
+  if (s != MPE_OK) return s;
+  copy_out(eig, p->host_res, p->m);
+  p->rr_cache_psi = psi;
+  return MPE_OK;
+}
+
+mpe_status mpe_residuals(mpe_plan p, const void* psi, const double* eig, double* rh, double* re) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (!psi || !eig || !rh) return fail(p, MPE_ERR_INVALID_ARGUMENT, "null array");
+  if (p->rr_cache_psi != psi) {
+    mpe_status s = run_h(p, psi, p->hphi);
+    if (s != MPE_OK) return s;
+    p->rr_cache_psi = psi;
+  }
+  // values to the device (theta slot), then R^H partials
+  HIPCHK(p, hipMemcpyAsync(p->scratch(), eig, sizeof(double) * p->m, hipMemcpyHostToDevice, p->st));
+  long chunk;
+  const int nch = rot_chunks(p, &chunk);
+  Timer t;
+  tic(p, t, MPE_KC_OTHER);
+  if (p->dbl)
+    hipLaunchKernelGGL(residual_kernel<double>, dim3(nch, p->m), dim3(256), 0, p->st, (const double*)psi,
+                       (const double*)p->hphi, (const double*)p->scratch(), p->N, chunk, p->mp, p->partials);
+  else
+    hipLaunchKernelGGL(residual_kernel<float>, dim3(nch, p->m), dim3(256), 0, p->st, (const float*)psi,
+                       (const float*)p->hphi, (const double*)p->scratch(), p->N, chunk, p->mp, p->partials);
+  HIPCHK(p, hipGetLastError());
+  HIPCHK(p, launch_reduce(p->partials, nch, (long)p->mp, 1, p->rh(), p->st));
+  toc(p, t);
+  if (re) {
+    if (p->last_dt <= 0) return fail(p, MPE_ERR_STATE, "R^E needs a previous step size");
+    mpe_status s = run_step(p, psi, p->phi, p->last_dt);
+    if (s != MPE_OK) return s;
+    const void* X[2] = {p->phi, psi};
+    const void* Y[2] = {p->phi, p->phi};
+    s = run_gram(p, X, Y, 2, p->S());   // S = phi phi^T, Hs slot = psi phi^T
+    if (s != MPE_OK) return s;
+    HIPCHK(p, launch_variance(p->S(), p->Hs(), p->m, p->mp, p->re(), p->reperp(), p->st));
+  }
+  // the H psi cache stays valid (psi unchanged)
+  HIPCHK(p, hipMemsetAsync(p->status, 0, 4 * sizeof(int), p->st));
+  mpe_status s = fetch(p);
+  if (s != MPE_OK) return s;
+  copy_out(rh, p->host_res + MAXM, p->m);
+  if (re) copy_out(re, p->host_res + 2 * MAXM, p->m);
+  return MPE_OK;
+}
+
+mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh, double* re, double* re_perp) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (!psi) return fail(p, MPE_ERR_INVALID_ARGUMENT, "psi is null");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, MPE_ERR_INVALID_ARGUMENT, "dt must be positive");
+  p->rr_cache_psi = nullptr;
+  mpe_status s = run_step(p, psi, p->phi, dt);
+  if (s == MPE_OK) s = run_h(p, p->phi, p->hphi);
+  const void* X[3] = {p->phi, p->phi, psi};
+  const void* Y[3] = {p->phi, p->hphi, p->phi};
+  if (s == MPE_OK) s = run_gram(p, X, Y, 3, p->S());   // S, Hs, M contiguous
+  if (s == MPE_OK) {
+    hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, p->re(), p->reperp(), p->st);
+    if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));
+  }
+  if (s == MPE_OK) s = run_small_dense(p, SD_RR);
+  if (s == MPE_OK) s = run_rotate(p, p->phi, p->hphi, psi, p->hphi);
+  if (s != MPE_OK) return s;
+  s = fetch(p);
+  if (s != MPE_OK) return s;
+  s = status_to_error(p);
+  if (s != MPE_OK) return s;
+  copy_out(eig, p->host_res, p->m);
+  copy_out(rh, p->host_res + MAXM, p->m);
+  copy_out(re, p->host_res + 2 * MAXM, p->m);
+  copy_out(re_perp, p->host_res + 3 * MAXM, p->m);
+  p->rr_cache_psi = psi;   // hphi now holds H psi (rotated)
+  return MPE_OK;
+}
+
+mpe_status mpe_set_states_per_launch(mpe_plan p, int32_t states) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (states < 0) return fail(p, MPE_ERR_INVALID_ARGUMENT, "states must be >= 0");
+  p->states_per_launch = states;
+  return MPE_OK;
+}
+
+mpe_status mpe_profile_enable(mpe_plan p, int32_t on) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  collect_times(p);
+  p->prof = on != 0;
+  return MPE_OK;
+}
+
+mpe_status mpe_get_kernel_times(mpe_plan p, double* ms, int64_t* launches) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  collect_times(p);
+  for (int i = 0; i < MPE_KC_COUNT; ++i) {
+    if (ms) ms[i] = p->kms[i];
+    if (launches) launches[i] = p->kcount[i];
+    p->kms[i] = 0;
+    p->kcount[i] = 0;
+  }
+  return MPE_OK;
+}
+
+}  // extern "C"

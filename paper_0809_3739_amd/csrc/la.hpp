@@ -1,0 +1,57 @@
+// Host-visible descriptors of the subspace linear-algebra kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mpe {
+
+constexpr int MAXM = 128;  // states (incl. guards) per system handled by one plan
+
+enum SmallDenseMode { SD_ORTHO = 0, SD_RR = 1 };
+enum SmallDenseStatus { ST_OK = 0, ST_NOT_SPD = 1, ST_EIG_NO_CONV = 2, ST_NONFINITE = 3 };
+
+// partial[prod][chunk][mp][mp] = X_prod Y_prod^T over the chunk's points
+struct GramArgs {
+  const void* X[3];
+  const void* Y[3];
+  double* partials;
+  long N;
+  long chunk;
+  int m, mp;
+};
+
+struct SmallDenseArgs {
+  const double* S;      // mp x mp overlap
+  const double* Hs;     // mp x mp projected H (SD_RR)
+  double* L;            // mp x mp workspace (Cholesky factor)
+  double* rot;          // rotation log, 4 doubles per rotation
+  double* scratch;      // >= 2*MAXM doubles
+  double* C;            // out: mp x mp, Psi_j = sum_i C[i][j] Phi_i
+  double* theta;        // out: m Ritz values ascending (SD_RR)
+  int* status;          // out: [code, detail]
+  int m, mp, mode, max_sweeps;
+  double tol;           // Jacobi: converged when |a_ij| <= tol * max(sqrt|a_ii a_jj|, floor)
+  double pivot_tol;     // Cholesky: pivot must exceed pivot_tol * original diagonal
+};
+
+struct RotateArgs {
+  const void* Phi;
+  const void* HPhi;     // may be null when no H rotation is wanted
+  const double* C;      // mp x mp
+  const double* theta;  // m (with H)
+  void* Psi;            // out
+  void* HPsi;           // optional out
+  double* res_partials; // [chunk][mp]
+  const int* status;    // small-dense status; the kernel does nothing unless it is ST_OK
+  long N;
+  long chunk;
+  int m, mp;
+};
+
+hipError_t launch_gram(int is_double, const GramArgs& g, int nprod, int nchunks, hipStream_t st);
+hipError_t launch_reduce(const double* in, int nparts, long count, int ncomp, double* out, hipStream_t st);
+hipError_t launch_small_dense(const SmallDenseArgs& d, hipStream_t st);
+hipError_t launch_rotate(int is_double, bool with_h, const RotateArgs& r, int nchunks, hipStream_t st);
+hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
+hipError_t launch_variance(const double* S, const double* M, int m, int mp, double* re, double* re_perp, hipStream_t st);
+
+}  // namespace mpe

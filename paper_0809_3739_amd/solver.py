@@ -1,0 +1,190 @@
+"""Python front end of libmpe: a Plan over torch device tensors and the
+step-size protocol of Section III (host logic; every array operation runs in
+the library's HIP kernels).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+
+PRECISIONS = {"fp64": _lib.MPE_FP64, "fp32": _lib.MPE_FP32}
+DTYPES = {"fp64": torch.float64, "fp32": torch.float32}
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Plan:
+    """An MPE plan on the current HIP device.
+
+    grid = (nx, ny, nz), box = (Lx, Ly, Lz); order = 2K; the state block has
+    m = n_states + n_guard states, a torch tensor of shape (m, nz, ny, nx) and
+    dtype float64 ("fp64") or float32 ("fp32") on the GPU.
+    """
+
+    def __init__(self, grid, box, n_states: int, order: int, precision: str = "fp64", n_guard: int = 0,
+                 stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmpe needs a HIP device (torch.cuda.is_available() is False)")
+        self.lib = _lib.lib()
+        self.grid = tuple(int(g) for g in grid)
+        self.box = tuple(float(b) for b in box)
+        self.n_states, self.n_guard = int(n_states), int(n_guard)
+        self.m = self.n_states + self.n_guard
+        self.order = int(order)
+        self.precision = precision
+        self.dtype = DTYPES[precision]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        g = (C.c_int32 * 3)(*self.grid)
+        b = (C.c_double * 3)(*self.box)
+        h = C.c_void_p()
+        code = self.lib.mpe_plan_create(C.byref(h), g, b, self.n_states, self.order, PRECISIONS[precision],
+                                        self.n_guard, C.c_void_p(self.stream.cuda_stream))
+        _lib.check(code)
+        self.h = h
+        self.shape = (self.m, self.grid[2], self.grid[1], self.grid[0])
+
+    # --------------------------------------------------------------- plumbing
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mpe_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, code):
+        _lib.check(code, self.h)
+
+    def _arr(self, t: torch.Tensor, shape=None):
+        shape = self.shape if shape is None else shape
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == self.dtype and tuple(t.shape) == shape):
+            raise ValueError(f"expected a contiguous {self.dtype} CUDA tensor of shape {shape}, got "
+                             f"{t.dtype} {tuple(t.shape)} cuda={t.is_cuda} contiguous={t.is_contiguous()}")
+        return C.c_void_p(t.data_ptr())
+
+    def new_states(self, data=None) -> torch.Tensor:
+        """A state block on the device (zeros, or a copy of ``data``)."""
+        if data is None:
+            return torch.zeros(self.shape, dtype=self.dtype, device="cuda")
+        t = torch.as_tensor(np.ascontiguousarray(data)).to(device="cuda", dtype=self.dtype)
+        return t.reshape(self.shape).contiguous()
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.lib.mpe_workspace_bytes(self.h))
+
+    # --------------------------------------------------------------- the C-ABI calls
+    def set_potential(self, V, hbar2_over_m: float = 1.0):
+        Vt = torch.as_tensor(np.ascontiguousarray(V) if isinstance(V, np.ndarray) else V)
+        Vt = Vt.to(device="cuda", dtype=torch.float64).contiguous()
+        if tuple(Vt.shape) != self.shape[1:]:
+            raise ValueError(f"V must have shape {self.shape[1:]}")
+        self._V = Vt   # keep alive until the copy has run
+        self._check(self.lib.mpe_set_potential(self.h, C.c_void_p(Vt.data_ptr()), float(hbar2_over_m)))
+
+    def step(self, psi: torch.Tensor, dt: float):
+        self._check(self.lib.mpe_step(self.h, self._arr(psi), float(dt)))
+
+    def apply_h(self, psi: torch.Tensor, hpsi: torch.Tensor | None = None) -> torch.Tensor:
+        out = torch.empty_like(psi) if hpsi is None else hpsi
+        self._check(self.lib.mpe_apply_h(self.h, self._arr(psi), self._arr(out)))
+        return out
+
+    def orthonormalize(self, psi: torch.Tensor):
+        self._check(self.lib.mpe_orthonormalize(self.h, self._arr(psi)))
+
+    def rayleigh_ritz(self, psi: torch.Tensor) -> np.ndarray:
+        eig = np.zeros(self.m)
+        self._check(self.lib.mpe_rayleigh_ritz(self.h, self._arr(psi), _dptr(eig)))
+        return eig
+
+    def residuals(self, psi: torch.Tensor, eig, with_re: bool = False):
+        eig = np.ascontiguousarray(eig, dtype=np.float64)
+        rh = np.zeros(self.m)
+        re = np.zeros(self.m) if with_re else None
+        self._check(self.lib.mpe_residuals(self.h, self._arr(psi), _dptr(eig), _dptr(rh),
+                                           _dptr(re) if with_re else None))
+        return (rh, re) if with_re else rh
+
+    def iterate(self, psi: torch.Tensor, dt: float) -> dict:
+        out = {k: np.zeros(self.m) for k in ("eig", "rh", "re", "re_perp")}
+        self._check(self.lib.mpe_iterate(self.h, self._arr(psi), float(dt), _dptr(out["eig"]), _dptr(out["rh"]),
+                                         _dptr(out["re"]), _dptr(out["re_perp"])))
+        return out
+
+    def set_states_per_launch(self, states: int):
+        self._check(self.lib.mpe_set_states_per_launch(self.h, int(states)))
+
+    def profile(self, on: bool = True):
+        self._check(self.lib.mpe_profile_enable(self.h, 1 if on else 0))
+
+    def kernel_times(self) -> dict:
+        ms = (C.c_double * len(_lib.KERNEL_CLASSES))()
+        cnt = (C.c_int64 * len(_lib.KERNEL_CLASSES))()
+        self._check(self.lib.mpe_get_kernel_times(self.h, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
+
+# ------------------------------------------------------------------ step-size protocol
+@dataclass
+class SolveResult:
+    eig: np.ndarray
+    rh: np.ndarray
+    dt: float
+    iterations: int
+    levels: int
+    converged: bool
+    seconds: float
+    history: list = field(default_factory=list)
+
+
+def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, reduce: float = 0.5,
+          n_check: int | None = None, margin: float = 0.01, max_iter_per_level: int = 2000,
+          max_levels: int = 30, orthonormalize_first: bool = True, callback=None) -> SolveResult:
+    """Iterate with the protocol of Section III until R^H_j < gamma for the
+    first ``n_check`` states.
+
+    At each dt the fused iteration is repeated until the basis-invariant
+    variance with respect to the evolution operator satisfies
+    max_j R^E_perp_j <= margin * gamma * dt^2 (R^E_perp/dt^2 is on the scale
+    of the part of R^H still removable at this dt); then R^H decides between
+    stopping and dt <- reduce * dt with the current states as the new start.
+    """
+    n_check = plan.n_states if n_check is None else n_check
+    t0 = time.perf_counter()
+    if orthonormalize_first:
+        plan.orthonormalize(psi)
+    dt = dt0
+    hist = []
+    total = 0
+    out = None
+    for level in range(max_levels):
+        ge = margin * gamma * dt * dt
+        for it in range(max_iter_per_level):
+            out = plan.iterate(psi, dt)
+            total += 1
+            rep = float(np.max(out["re_perp"][:n_check]))
+            rhm = float(np.max(out["rh"][:n_check]))
+            hist.append({"dt": dt, "it": total, "re_perp": rep, "rh": rhm, "eig0": float(out["eig"][0]),
+                         "t": time.perf_counter() - t0})
+            if callback:
+                callback(hist[-1])
+            if rhm < gamma:
+                break
+            if it > 0 and rep <= ge:
+                break
+        if float(np.max(out["rh"][:n_check])) < gamma:
+            return SolveResult(out["eig"], out["rh"], dt, total, level + 1, True, time.perf_counter() - t0, hist)
+        dt *= reduce
+    return SolveResult(out["eig"], out["rh"], dt, total, max_levels, False, time.perf_counter() - t0, hist)

@@ -1,0 +1,298 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Every case prints its name, grid, precision and seed before touching the GPU.
+Tolerances (relative to the largest reference magnitude unless stated):
+
+* float64 path: 1e-12 * sum_k |c_k| for a step (transform roundoff ~1e-16 per
+  pass times the amplification of the alternating combination, Eq. coef),
+  1e-12 for H, overlaps, Cholesky and Rayleigh-Ritz.
+* float32 path: STEP32 * sum_k |c_k| per step, where STEP32 bounds the relative
+  error of one float32 chain (3-D transform roundoff ~ eps32 * log2 N per T2
+  plus one rounding of every table entry); 2e-6 for H and the rotations.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mpe as oracle
+from oracle import dense
+
+pytestmark = pytest.mark.gpu
+
+STEP64 = 1e-12
+STEP32 = 4e-6
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_0809_3739_amd as P
+    P.lib()
+    return P
+
+
+def toy_potential(grid, box):
+    Z, Y, X = W.mesh(grid, box)
+    L = min(box)
+    return (0.5 * (X * X + Y * Y + Z * Z) * (8.0 / L) ** 2
+            - 1.5 * np.exp(-((X - 0.7) ** 2 + (Y + 0.3) ** 2 + (Z - 0.4) ** 2)))
+
+
+def sum_abs_c(order):
+    return float(sum(abs(c) for c in oracle.mpe_coefficients_exact(order // 2)))
+
+
+def rel_err(got, ref):
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def rounded(a, prec):
+    return a.astype(np.float32).astype(np.float64) if prec == "fp32" else a
+
+
+STEP_CASES = [
+    ((8, 8, 8), (8.0, 8.0, 8.0), 3, 2, "fp64", 0.2),
+    ((16, 16, 16), (10.0, 10.0, 10.0), 3, 4, "fp64", 0.3),
+    ((32, 32, 32), (16.0, 16.0, 16.0), 4, 6, "fp64", 0.3),
+    ((48, 48, 48), (12.0, 12.0, 12.0), 2, 4, "fp64", 0.25),
+    ((64, 64, 32), (12.0, 12.0, 9.0), 2, 12, "fp64", 0.5),
+    ((96, 96, 16), (12.0, 12.0, 8.0), 2, 4, "fp64", 0.2),
+    ((16, 16, 96), (8.0, 8.0, 12.0), 2, 4, "fp64", 0.2),
+    ((128, 128, 8), (16.0, 16.0, 8.0), 2, 8, "fp64", 0.4),
+    ((32, 32, 48), (12.0, 12.0, 14.0), 3, 8, "fp32", 0.3),
+    ((64, 64, 64), (12.0, 12.0, 12.0), 2, 12, "fp32", 0.5),
+    ((128, 128, 128), (32.0, 32.0, 32.0), 2, 12, "fp32", 0.5),
+    ((192, 192, 16), (24.0, 24.0, 8.0), 1, 4, "fp32", 0.2),
+    ((8, 8, 192), (8.0, 8.0, 24.0), 2, 4, "fp32", 0.2),
+]
+
+
+@pytest.mark.parametrize("grid,box,m,order,prec,dt", STEP_CASES, ids=[f"{c[0]}-o{c[3]}-{c[4]}" for c in STEP_CASES])
+def test_step_matches_oracle(P, grid, box, m, order, prec, dt):
+    say("step", grid, box, m, order, prec, dt)
+    V = toy_potential(grid, box)
+    psi0 = rounded(W.random_states(17, m, grid), prec)
+    plan = P.Plan(grid, box, m, order, prec)
+    plan.set_potential(V)
+    psi = plan.new_states(psi0)
+    plan.step(psi, dt)
+    got = psi.cpu().numpy().astype(np.float64)
+    ref = oracle.mpe_apply(psi0, V, dt, order // 2, grid, box)
+    err = rel_err(got, ref)
+    tol = (STEP64 if prec == "fp64" else STEP32) * sum_abs_c(order)
+    say("  rel err", err, "tol", tol)
+    assert err < tol
+
+
+H_CASES = [((8, 8, 8), "fp64"), ((32, 32, 16), "fp64"), ((48, 48, 64), "fp64"), ((128, 128, 32), "fp64"),
+           ((96, 96, 96), "fp32"), ((192, 192, 8), "fp32")]
+
+
+@pytest.mark.parametrize("grid,prec", H_CASES, ids=[f"{c[0]}-{c[1]}" for c in H_CASES])
+def test_apply_h_matches_oracle(P, grid, prec):
+    box = tuple(0.25 * g + 2.0 for g in grid)
+    say("apply_h", grid, box, prec)
+    V = toy_potential(grid, box)
+    m = 3
+    psi0 = rounded(W.random_states(5, m, grid), prec)
+    plan = P.Plan(grid, box, m, 2, prec)
+    plan.set_potential(V, hbar2_over_m=0.8)
+    psi = plan.new_states(psi0)
+    h = plan.apply_h(psi).cpu().numpy().astype(np.float64)
+    ref = oracle.h_apply(psi0, V, grid, box, hbar2_over_m=0.8)
+    err = rel_err(h, ref)
+    say("  rel err", err)
+    assert err < (1e-12 if prec == "fp64" else 2e-6)
+    # the input block is left untouched
+    assert np.array_equal(psi.cpu().numpy().astype(np.float64), psi0)
+
+
+@pytest.mark.parametrize("prec,m,grid", [("fp64", 10, (32, 32, 32)), ("fp64", 125, (16, 16, 16)),
+                                         ("fp32", 37, (32, 32, 32))])
+def test_orthonormalize_matches_cholesky_qr(P, prec, m, grid):
+    say("orthonormalize", prec, m, grid)
+    box = (10.0, 10.0, 10.0)
+    phi0 = rounded(W.random_states(23, m, grid), prec)
+    plan = P.Plan(grid, box, m, 2, prec)
+    psi = plan.new_states(phi0)
+    plan.orthonormalize(psi)
+    got = psi.cpu().numpy().astype(np.float64)
+    ref, _, _ = oracle.cholesky_orthonormalize(phi0)
+    err = rel_err(got, ref)
+    G = got.reshape(m, -1) @ got.reshape(m, -1).T
+    say("  rel err", err, "orth", np.abs(G - np.eye(m)).max())
+    assert err < (1e-12 if prec == "fp64" else 2e-6)
+    assert np.abs(G - np.eye(m)).max() < (1e-13 if prec == "fp64" else 2e-6)
+
+
+def _align_signs(got, ref):
+    g = got.reshape(got.shape[0], -1)
+    r = ref.reshape(ref.shape[0], -1)
+    s = np.sign(np.einsum("ij,ij->i", g, r))
+    return (g * s[:, None]).reshape(got.shape)
+
+
+@pytest.mark.parametrize("prec,m,grid", [("fp64", 8, (16, 16, 16)), ("fp64", 125, (16, 16, 16)),
+                                         ("fp32", 20, (32, 32, 32))])
+def test_rayleigh_ritz_matches_oracle(P, prec, m, grid):
+    say("rayleigh_ritz", prec, m, grid)
+    box = (10.0, 10.0, 10.0)
+    V = toy_potential(grid, box)
+    # a smooth-ish subspace: a few T2 steps of random states, orthonormalised by the oracle
+    phi = W.random_states(29, m, grid)
+    for _ in range(3):
+        phi = oracle.t2(phi, V, 0.3, grid, box)
+    Psi0, _, _ = oracle.cholesky_orthonormalize(phi)
+    Psi0 = rounded(Psi0, prec)
+    plan = P.Plan(grid, box, m, 2, prec)
+    plan.set_potential(V)
+    psi = plan.new_states(Psi0)
+    eig = plan.rayleigh_ritz(psi)
+    theta, Pr, HPr, _ = oracle.rayleigh_ritz(Psi0, oracle.h_apply(Psi0, V, grid, box))
+    say("  eig err", np.max(np.abs(eig - theta)) / np.max(np.abs(theta)))
+    assert np.max(np.abs(eig - theta)) < (1e-11 if prec == "fp64" else 2e-5) * np.max(np.abs(theta))
+    got = psi.cpu().numpy().astype(np.float64)
+    # vectors are unique up to sign where the Ritz values are separated
+    gaps = np.diff(theta)
+    sep = np.ones(m, bool)
+    sep[:-1] &= gaps > 1e-3
+    sep[1:] &= gaps > 1e-3
+    al = _align_signs(got, Pr)
+    err = np.max(np.abs(al[sep] - Pr[sep])) / np.max(np.abs(Pr))
+    say("  vec err (separated)", err, int(sep.sum()))
+    assert err < (1e-9 if prec == "fp64" else 1e-4)
+    rh = plan.residuals(psi, eig)
+    rh_ref = oracle.residual_h(Pr, HPr, theta)
+    assert np.allclose(rh[sep], rh_ref[sep], rtol=1e-6 if prec == "fp64" else 1e-2, atol=1e-20)
+
+
+def test_iterate_lockstep_oscillator(P):
+    """Config-1 geometry: 32^3 oscillator, 10 states, order 4, dt = 0.1, float64, lockstep."""
+    s = W.harmonic_system(32, 16.0, 10)
+    say("iterate lockstep", s.grid)
+    psi0 = W.random_states(0, 10, s.grid)
+    ref, _, _ = oracle.cholesky_orthonormalize(psi0)
+    plan = P.Plan(s.grid, s.box, 10, 4, "fp64")
+    plan.set_potential(s.V)
+    psi = plan.new_states(psi0)
+    plan.orthonormalize(psi)
+    for it in range(6):
+        out = plan.iterate(psi, 0.1)
+        r = oracle.iterate(ref, s.V, 0.1, 2, s.grid, s.box)
+        ref = r.psi
+        e = np.max(np.abs(out["eig"] - r.theta) / np.abs(r.theta))
+        got = psi.cpu().numpy()
+        Pg = got.reshape(10, -1)
+        Pr = ref.reshape(10, -1)
+        proj = np.linalg.norm(Pg.T @ (Pg @ Pr.T) - Pr.T) / math.sqrt(10)
+        say(f"  it {it} eig rel {e:.2e} proj {proj:.2e} rh {out['rh'].max():.3e}/{r.rh.max():.3e}")
+        assert e < 1e-10
+        assert proj < 1e-9
+        np.testing.assert_allclose(out["re_perp"], r.re_perp, rtol=1e-6, atol=1e-14)
+        np.testing.assert_allclose(out["rh"].sum(), r.rh.sum(), rtol=1e-6)
+
+
+@pytest.mark.parametrize("prec,order,tol", [("fp64", 4, 1e-10), ("fp32", 4, 1e-6), ("fp64", 2, 1e-10)])
+def test_solve_oscillator_to_exact_levels(P, prec, order, tol):
+    """The oscillator levels 1.5, 2.5 x3, 3.5 x6 (exact grid values by separable diagonalisation)."""
+    s = W.harmonic_system(32, 16.0, 10)
+    say("solve oscillator", prec, order)
+    plan = P.Plan(s.grid, s.box, 10, order, prec)
+    plan.set_potential(s.V)
+    psi = plan.new_states(W.random_states(1, 10, s.grid))
+    gamma = 1e-10
+    res = P.solve(plan, psi, dt0=0.1, gamma=gamma)
+    exact = dense.separable_oscillator_levels(32, 16.0, 10)
+    say("  iters", res.iterations, "levels", res.levels, "dt", res.dt, "max rel",
+        np.max(np.abs(res.eig[:10] - exact) / exact), "rh", res.rh.max())
+    assert res.converged
+    assert np.max(np.abs(res.eig[:10] - exact) / exact) < tol
+
+
+def test_not_positive_definite_leaves_states(P):
+    grid, box = (16, 16, 16), (8.0, 8.0, 8.0)
+    say("error path: duplicate states")
+    psi0 = W.random_states(3, 4, grid)
+    psi0[2] = psi0[1]
+    plan = P.Plan(grid, box, 4, 2, "fp64")
+    psi = plan.new_states(psi0)
+    with pytest.raises(P.MpeError) as ei:
+        plan.orthonormalize(psi)
+    assert ei.value.name == "MPE_ERR_NOT_POSITIVE_DEFINITE"
+    assert np.array_equal(psi.cpu().numpy(), psi0)
+
+
+def test_nonfinite_reported(P):
+    grid, box = (16, 16, 16), (8.0, 8.0, 8.0)
+    say("error path: NaN state")
+    psi0 = W.random_states(3, 4, grid)
+    psi0[1, 3, 4, 5] = np.nan
+    plan = P.Plan(grid, box, 4, 2, "fp64")
+    psi = plan.new_states(psi0)
+    with pytest.raises(P.MpeError) as ei:
+        plan.orthonormalize(psi)
+    assert ei.value.name in ("MPE_ERR_NONFINITE", "MPE_ERR_NOT_POSITIVE_DEFINITE")
+    assert np.array_equal(np.isnan(psi.cpu().numpy()), np.isnan(psi0))
+
+
+def test_step_requires_potential_and_positive_dt(P):
+    say("error path: call order")
+    plan = P.Plan((16, 16, 16), (8.0, 8.0, 8.0), 2, 2, "fp64")
+    psi = plan.new_states(W.random_states(0, 2, (16, 16, 16)))
+    with pytest.raises(P.MpeError) as ei:
+        plan.step(psi, 0.1)
+    assert ei.value.name == "MPE_ERR_STATE"
+    plan.set_potential(np.zeros((16, 16, 16)))
+    with pytest.raises(P.MpeError):
+        plan.step(psi, -0.1)
+
+
+def test_deterministic_and_launch_grouping_invariant(P):
+    grid, box = (32, 32, 32), (12.0, 12.0, 12.0)
+    say("determinism / states per launch")
+    V = toy_potential(grid, box)
+    psi0 = W.random_states(8, 6, grid)
+    outs = []
+    for spl in (0, 0, 1, 4):
+        plan = P.Plan(grid, box, 6, 6, "fp32")
+        plan.set_potential(V)
+        plan.set_states_per_launch(spl)
+        psi = plan.new_states(psi0)
+        plan.orthonormalize(psi)
+        r = plan.iterate(psi, 0.3)
+        outs.append((psi.cpu().numpy(), r["eig"]))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert np.array_equal(o[1], outs[0][1])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_full_size_c60_step_sampled(P, prec):
+    """128^3 C60-like cage, 125 states, order 12 -- one step in the benchmark's launch
+    configuration; two sampled states are checked against the oracle one by one."""
+    s = W.c60_system(128, 32.0, 120)
+    m = 125
+    say("full-size step", prec, s.grid, m)
+    plan = P.Plan(s.grid, s.box, 120, 12, prec, n_guard=5)
+    plan.set_potential(s.V)
+    rng_states = W.random_states(0, m, s.grid)
+    psi = plan.new_states(rounded(rng_states, prec))
+    plan.step(psi, 0.5)
+    got = psi.cpu().numpy()
+    for j in (0, m - 1):
+        x0 = rounded(rng_states[j:j + 1], prec)
+        ref = oracle.mpe_apply(x0, s.V, 0.5, 6, s.grid, s.box)
+        err = rel_err(got[j:j + 1].astype(np.float64), ref)
+        tol = (STEP64 if prec == "fp64" else STEP32) * sum_abs_c(12)
+        say(f"  state {j} rel err {err:.3e} tol {tol:.1e}")
+        assert err < tol
