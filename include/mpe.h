@@ -136,6 +136,14 @@ mpe_status mpe_residuals(mpe_plan p, const void* psi, const double* eig, double*
  * left unchanged. */
 mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh, double* re, double* re_perp);
 
+/* Graph replay of mpe_iterate (on by default).  The first call for a given
+ * psi array captures the iteration's launches into a hipGraph on a private
+ * stream ordered after the plan's stream; later calls with the same psi and
+ * launch grouping replay it (dt enters through tables rebuilt outside the
+ * graph).  Off: every launch is enqueued eagerly. Kernel timing (below) uses
+ * the eager path. */
+mpe_status mpe_set_graph(mpe_plan p, int32_t on);
+
 /* Launch-shape knob: states per propagation launch (0 = all m). */
 mpe_status mpe_set_states_per_launch(mpe_plan p, int32_t states);
 

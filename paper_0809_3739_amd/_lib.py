@@ -43,6 +43,7 @@ SIGNATURES = {
     "mpe_residuals": (C.c_int, [_vp, _vp, _dp, _dp, _dp]),
     "mpe_iterate": (C.c_int, [_vp, _vp, C.c_double, _dp, _dp, _dp, _dp]),
     "mpe_set_states_per_launch": (C.c_int, [_vp, _i32]),
+    "mpe_set_graph": (C.c_int, [_vp, _i32]),
     "mpe_profile_enable": (C.c_int, [_vp, _i32]),
     "mpe_get_kernel_times": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64)]),
 }

@@ -157,9 +157,19 @@ struct mpe_plan_s {
   double last_dt = -1.0;
   int states_per_launch = 0;
   int max_sweeps = 60;
-  double jacobi_tol = 1e-14;
+  double jacobi_tol = 1e-13;
   double pivot_tol = 1e-13;
   const void* rr_cache_psi = nullptr;   // H psi cached in hphi for this psi
+
+  // graph replay of the fused iteration
+  bool use_graph = true;
+  hipStream_t gst = nullptr;         // private stream for capture and replay
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* g_psi = nullptr;       // the graph bakes in this state block ...
+  int g_spl = -1;                    // ... and this launch grouping
+  hipEvent_t ev_in = nullptr;
+  int64_t graph_launches = 0;
 
   // timing
   bool prof = false;
@@ -302,10 +312,8 @@ void* chain_spec(mpe_plan p, int k) {  // k = 0..K-1
   return (char*)p->W + (size_t)k * p->m * p->spec * p->cx_size();
 }
 
-// dst <- T_2K(dt) src, all m states (src may equal dst).
-mpe_status run_step(mpe_plan p, const void* src, void* dst, double dt) {
-  mpe_status s = ensure_tables(p, dt);
-  if (s != MPE_OK) return s;
+// dst <- T_2K(dt) src, all m states (src may equal dst); tables for dt must be current.
+mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
   const size_t f = p->fsz;
   double c[MAX_K];
   mpe_coeffs(p->K, c);
@@ -362,8 +370,15 @@ mpe_status run_step(mpe_plan p, const void* src, void* dst, double dt) {
            return launch_plane(p->dbl, PM_TAIL, p->nx, a, p->nz, cnt, p->st);
          }));
   toc(p, t);
-  p->last_dt = dt;
   return MPE_OK;
+}
+
+mpe_status run_step(mpe_plan p, const void* src, void* dst, double dt) {
+  mpe_status s = ensure_tables(p, dt);
+  if (s != MPE_OK) return s;
+  s = enqueue_step(p, src, dst);
+  if (s == MPE_OK) p->last_dt = dt;
+  return s;
 }
 
 // hdst <- H src (src != hdst); uses chain 0's spectrum buffer as scratch.
@@ -540,6 +555,69 @@ void host_roots(int L, std::vector<double>& out) {
   }
 }
 
+// Device work of one fused iteration on p->st, ending with the copy of the
+// results to the pinned mirror (no synchronisation).  Tables must be current.
+mpe_status enqueue_iterate(mpe_plan p, void* psi) {
+  mpe_status s = enqueue_step(p, psi, p->phi);
+  if (s == MPE_OK) s = run_h(p, p->phi, p->hphi);
+  const void* X[3] = {p->phi, p->phi, psi};
+  const void* Y[3] = {p->phi, p->hphi, p->phi};
+  if (s == MPE_OK) s = run_gram(p, X, Y, 3, p->S());   // S, Hs, M contiguous
+  if (s == MPE_OK) {
+    hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, p->re(), p->reperp(), p->st);
+    if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));
+  }
+  if (s == MPE_OK) s = run_small_dense(p, SD_RR);
+  if (s == MPE_OK) s = run_rotate(p, p->phi, p->hphi, psi, p->hphi);
+  if (s != MPE_OK) return s;
+  HIPCHK(p, hipMemcpyAsync(p->host_res, p->res, p->res_bytes, hipMemcpyDeviceToHost, p->st));
+  return MPE_OK;
+}
+
+void drop_graph(mpe_plan p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  p->g_psi = nullptr;
+  p->g_spl = -1;
+}
+
+// Capture enqueue_iterate(psi) on the private stream into an executable graph.
+mpe_status capture_iterate(mpe_plan p, void* psi) {
+  drop_graph(p);
+  if (!p->gst) HIPCHK(p, hipStreamCreateWithFlags(&p->gst, hipStreamNonBlocking));
+  if (!p->ev_in) HIPCHK(p, hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
+  HIPCHK(p, hipStreamBeginCapture(p->gst, hipStreamCaptureModeRelaxed));
+  hipStream_t user = p->st;
+  p->st = p->gst;
+  mpe_status s = enqueue_iterate(p, psi);
+  p->st = user;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(p->gst, &g);
+  if (s != MPE_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(p, MPE_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  p->graph = g;
+  HIPCHK(p, hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+  p->g_psi = psi;
+  p->g_spl = p->states_per_launch;
+  return MPE_OK;
+}
+
+mpe_status finish_iterate(mpe_plan p, void* psi, double* eig, double* rh, double* re, double* re_perp) {
+  mpe_status s = status_to_error(p);
+  if (s != MPE_OK) return s;
+  copy_out(eig, p->host_res, p->m);
+  copy_out(rh, p->host_res + MAXM, p->m);
+  copy_out(re, p->host_res + 2 * MAXM, p->m);
+  copy_out(re_perp, p->host_res + 3 * MAXM, p->m);
+  p->rr_cache_psi = psi;   // hphi now holds H psi (rotated)
+  return MPE_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ exported API
@@ -575,6 +653,9 @@ mpe_status mpe_plan_destroy(mpe_plan p) {
     (void)hipEventDestroy(t.b);
   }
   for (auto e : p->pool) (void)hipEventDestroy(e);
+  drop_graph(p);
+  if (p->ev_in) (void)hipEventDestroy(p->ev_in);
+  if (p->gst) (void)hipStreamDestroy(p->gst);
   void* bufs[] = {p->W, p->phi, p->hphi, p->V64, p->Vf, p->fac, p->kin, p->hk, p->roots,
                   p->partials, p->mats, p->rot, p->res};
   for (void* b : bufs)
@@ -668,6 +749,10 @@ mpe_status mpe_plan_create(mpe_plan* out, const int32_t grid[3], const double bo
     return MPE_ERR_OUT_OF_MEMORY;
   }
   p->status = reinterpret_cast<int*>(p->res + 6 * MAXM);
+  if (prepare_small_dense() != hipSuccess) {
+    mpe_plan_destroy(p);
+    return MPE_ERR_DEVICE;
+  }
   if (hipHostMalloc((void**)&p->host_res, p->res_bytes, hipHostMallocDefault) != hipSuccess) {
     mpe_plan_destroy(p);
     return MPE_ERR_OUT_OF_MEMORY;
@@ -816,27 +901,32 @@ mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh
   if (!psi) return fail(p, MPE_ERR_INVALID_ARGUMENT, "psi is null");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, MPE_ERR_INVALID_ARGUMENT, "dt must be positive");
   p->rr_cache_psi = nullptr;
-  mpe_status s = run_step(p, psi, p->phi, dt);
-  if (s == MPE_OK) s = run_h(p, p->phi, p->hphi);
-  const void* X[3] = {p->phi, p->phi, psi};
-  const void* Y[3] = {p->phi, p->hphi, p->phi};
-  if (s == MPE_OK) s = run_gram(p, X, Y, 3, p->S());   // S, Hs, M contiguous
-  if (s == MPE_OK) {
-    hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, p->re(), p->reperp(), p->st);
-    if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));
+  mpe_status s = ensure_tables(p, dt);
+  if (s != MPE_OK) return s;
+  p->last_dt = dt;
+  if (p->use_graph && !p->prof) {
+    if (!p->gexec || p->g_psi != psi || p->g_spl != p->states_per_launch) {
+      s = capture_iterate(p, psi);
+      if (s != MPE_OK) return s;
+    }
+    HIPCHK(p, hipEventRecord(p->ev_in, p->st));           // tables and earlier work on the user stream
+    HIPCHK(p, hipStreamWaitEvent(p->gst, p->ev_in, 0));
+    HIPCHK(p, hipGraphLaunch(p->gexec, p->gst));
+    HIPCHK(p, hipStreamSynchronize(p->gst));
+    p->graph_launches++;
+  } else {
+    s = enqueue_iterate(p, psi);
+    if (s != MPE_OK) return s;
+    HIPCHK(p, hipStreamSynchronize(p->st));
+    collect_times(p);
   }
-  if (s == MPE_OK) s = run_small_dense(p, SD_RR);
-  if (s == MPE_OK) s = run_rotate(p, p->phi, p->hphi, psi, p->hphi);
-  if (s != MPE_OK) return s;
-  s = fetch(p);
-  if (s != MPE_OK) return s;
-  s = status_to_error(p);
-  if (s != MPE_OK) return s;
-  copy_out(eig, p->host_res, p->m);
-  copy_out(rh, p->host_res + MAXM, p->m);
-  copy_out(re, p->host_res + 2 * MAXM, p->m);
-  copy_out(re_perp, p->host_res + 3 * MAXM, p->m);
-  p->rr_cache_psi = psi;   // hphi now holds H psi (rotated)
+  return finish_iterate(p, psi, eig, rh, re, re_perp);
+}
+
+mpe_status mpe_set_graph(mpe_plan p, int32_t on) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  p->use_graph = on != 0;
+  if (!p->use_graph) drop_graph(p);
   return MPE_OK;
 }
 

@@ -153,7 +153,7 @@ template <> struct Plan<16>  { static constexpr int E = 16, T = 1, S = 1, R0 = 1
 template <> struct Plan<24>  { static constexpr int E = 24, T = 1, S = 2, R0 = 3,  R1 = 8, R2 = 1; };
 template <> struct Plan<32>  { static constexpr int E = 8,  T = 4, S = 2, R0 = 8,  R1 = 4, R2 = 1; };
 template <> struct Plan<48>  { static constexpr int E = 12, T = 4, S = 3, R0 = 3,  R1 = 4, R2 = 4; };
-template <> struct Plan<64>  { static constexpr int E = 8,  T = 8, S = 2, R0 = 8,  R1 = 8, R2 = 1; };
+template <> struct Plan<64>  { static constexpr int E = 16, T = 4, S = 2, R0 = 16, R1 = 4, R2 = 1; };
 template <> struct Plan<96>  { static constexpr int E = 24, T = 4, S = 3, R0 = 3,  R1 = 4, R2 = 8; };
 template <> struct Plan<128> { static constexpr int E = 16, T = 8, S = 2, R0 = 16, R1 = 8, R2 = 1; };
 template <> struct Plan<192> { static constexpr int E = 24, T = 8, S = 3, R0 = 3,  R1 = 8, R2 = 8; };

@@ -240,25 +240,39 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   }
   __syncthreads();
 
-  // ---- cyclic Jacobi, round-robin ordering over n = m rounded up to even
+  // ---- cyclic Jacobi, round-robin ordering over n = m rounded up to even.
+  // One step rotates n/2 disjoint pairs at once.  A' = J^T A J is applied as
+  // independent 2x2 blocks: block (k, l) = rows {p_k, q_k} x columns {p_l, q_l}
+  // becomes J_k^T B J_l, so every element is read and written once per step.
   const int n = (m + 1) & ~1, half = n / 2;
-  // absolute floor for the relative off-diagonal test (eigenvalues near zero)
+  if (n > m) {   // zero padding row / column: the identity "rotations" of it stay exact
+    for (int i = tid; i < n; i += SD_THREADS) {
+      A(m, i) = 0.0;
+      A(i, m) = 0.0;
+    }
+  }
+  __shared__ int step_active[2];
+  if (tid == 0) step_active[0] = step_active[1] = 0;
+  __syncthreads();
+  // absolute floor: rotations regenerate off-diagonal roundoff of order eps * max|a_ii|.
+  // Rotations are applied above tol/8 and convergence is declared at tol, so the
+  // roundoff a rotation leaves behind cannot keep a sweep from finishing.
   double dmax = 0.0;
   for (int i = tid; i < m; i += SD_THREADS) dmax = fmax(dmax, fabs(A(i, i)));
-  // absolute floor: rotations regenerate off-diagonal roundoff of order eps * max|a_ii|
-  const double floor_abs = 8.0 * 2.220446049250313e-16 * fmax(block_max(dmax, red), 1e-300) / d.tol;
+  const double floor_abs = 32.0 * 2.220446049250313e-16 * fmax(block_max(dmax, red), 1e-300) / d.tol;
+  const double rot_tol = 0.125 * d.tol;
   long nrot = 0;
   int sweep = 0;
   bool converged = false;
+  int gstep = 0;
   for (; sweep < d.max_sweeps; ++sweep) {
-    // convergence test: every off-diagonal |a_ij| <= tol * sqrt(|a_ii a_jj|)
+    // convergence test: every off-diagonal |a_ij| <= tol * max(sqrt(|a_ii a_jj|), floor)
     double worst = 0.0;
     for (int e = tid; e < m * m; e += SD_THREADS) {
       const int i = e / m, j = e % m;
       if (i != j) {
         const double den = fmax(sqrt(fabs(A(i, i) * A(j, j))), floor_abs);
-        const double r = fabs(A(i, j)) / den;
-        worst = fmax(worst, r);
+        worst = fmax(worst, fabs(A(i, j)) / den);
       }
     }
     worst = block_max(worst, red);
@@ -266,8 +280,9 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
       converged = true;
       break;
     }
-    for (int step = 0; step < n - 1; ++step) {
-      // pairs of this step and their rotations
+    for (int step = 0; step < n - 1; ++step, ++gstep) {
+      const int cur = gstep & 1;
+      if (tid == 0) step_active[cur ^ 1] = 0;   // last read before the previous step's final barrier
       for (int k = tid; k < half; k += SD_THREADS) {
         int p, q;
         if (k == 0) {
@@ -278,51 +293,47 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
           q = ((n - 1 - k + step) % (n - 1)) + 1;
         }
         if (p > q) { const int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
+        double c = 1.0, sn = 0.0;
         if (q < m) {
           const double apq = A(p, q), app = A(p, p), aqq = A(q, q);
-          if (fabs(apq) > d.tol * fmax(sqrt(fabs(app * aqq)), floor_abs) && apq != 0.0) {
+          if (fabs(apq) > rot_tol * fmax(sqrt(fabs(app * aqq)), floor_abs) && apq != 0.0) {
             const double th = (aqq - app) / (2.0 * apq);
             const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
             c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            sn = t * c;
+            step_active[cur] = 1;
           }
         }
         cs[k][0] = c;
-        cs[k][1] = s;
+        cs[k][1] = sn;
         pq[k][0] = p;
         pq[k][1] = q;
-        const long slot = (nrot + k) * 4;
-        d.rot[slot + 0] = c;
-        d.rot[slot + 1] = s;
-        d.rot[slot + 2] = (double)p;
-        d.rot[slot + 3] = (double)q;
       }
       __syncthreads();
-      // rows p, q <- J^T rows
-      for (int e = tid; e < half * m; e += SD_THREADS) {
-        const int k = e / m, r = e % m;
-        const int p = pq[k][0], q = pq[k][1];
-        if (q < m) {
-          const double c = cs[k][0], s = cs[k][1];
-          const double ap = A(p, r), aq = A(q, r);
-          A(p, r) = c * ap - s * aq;
-          A(q, r) = s * ap + c * aq;
+      if (step_active[cur]) {   // uniform
+        for (int k = tid; k < half; k += SD_THREADS) {
+          double* slot = d.rot + (nrot + k) * 4;
+          slot[0] = cs[k][0];
+          slot[1] = cs[k][1];
+          slot[2] = (double)pq[k][0];
+          slot[3] = (double)pq[k][1];
         }
-      }
-      __syncthreads();
-      // columns p, q <- columns J
-      for (int e = tid; e < half * m; e += SD_THREADS) {
-        const int k = e / m, r = e % m;
-        const int p = pq[k][0], q = pq[k][1];
-        if (q < m) {
-          const double c = cs[k][0], s = cs[k][1];
-          const double ap = A(r, p), aq = A(r, q);
-          A(r, p) = c * ap - s * aq;
-          A(r, q) = s * ap + c * aq;
+        for (int e = tid; e < half * half; e += SD_THREADS) {
+          const int k = e / half, l = e - k * half;
+          const int pk = pq[k][0], qk = pq[k][1], pl = pq[l][0], ql = pq[l][1];
+          const double ck = cs[k][0], sk = cs[k][1], cl = cs[l][0], sl = cs[l][1];
+          const double b00 = A(pk, pl), b01 = A(pk, ql), b10 = A(qk, pl), b11 = A(qk, ql);
+          // rows: J_k^T
+          const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
+          const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
+          // columns: J_l
+          A(pk, pl) = cl * r00 - sl * r01;
+          A(pk, ql) = sl * r00 + cl * r01;
+          A(qk, pl) = cl * r10 - sl * r11;
+          A(qk, ql) = sl * r10 + cl * r11;
         }
+        nrot += half;
       }
-      nrot += half;
       __syncthreads();
     }
   }
@@ -522,15 +533,13 @@ hipError_t launch_reduce(const double* in, int nparts, long count, int ncomp, do
   return hipGetLastError();
 }
 
+hipError_t prepare_small_dense() {
+  return hipFuncSetAttribute((const void*)small_dense_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)((size_t)MAXM * (MAXM + 1) * sizeof(double)));
+}
+
 hipError_t launch_small_dense(const SmallDenseArgs& d, hipStream_t st) {
   const size_t lds = (size_t)d.mp * (d.mp + 1) * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    const hipError_t e = hipFuncSetAttribute((const void*)small_dense_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)((size_t)MAXM * (MAXM + 1) * sizeof(double)));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
   hipLaunchKernelGGL(small_dense_kernel, dim3(1), dim3(SD_THREADS), lds, st, d);
   return hipGetLastError();
 }

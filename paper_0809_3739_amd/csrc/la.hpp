@@ -49,6 +49,7 @@ struct RotateArgs {
 
 hipError_t launch_gram(int is_double, const GramArgs& g, int nprod, int nchunks, hipStream_t st);
 hipError_t launch_reduce(const double* in, int nparts, long count, int ncomp, double* out, hipStream_t st);
+hipError_t prepare_small_dense();
 hipError_t launch_small_dense(const SmallDenseArgs& d, hipStream_t st);
 hipError_t launch_rotate(int is_double, bool with_h, const RotateArgs& r, int nchunks, hipStream_t st);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st);

@@ -23,73 +23,59 @@
 
 namespace mpe {
 
-// ------------------------------------------------------------------ real <-> half-spectrum split steps
-// Row r holds Z = FFT_{NX/2}(x[2i] + i x[2i+1]) in slots 0..LX-1; afterwards
-// slots 0..LX hold X = the NX-point real-input DFT (exact scaling).
-template <typename F, int NX, int NY, int BLOCK>
-__device__ __forceinline__ void r2c_split(cx<F>* lds, const cx<F>* __restrict__ wpost) {
-  constexpr int LX = NX / 2, NXH = LX + 1, NP = LX / 2 + 1;
-  for (int task = threadIdx.x; task < NY * NP; task += BLOCK) {
-    const int row = task / NP, k = task - row * NP;
-    cx<F>* r = lds + row * NXH;
-    if (k == 0) {
-      const cx<F> z = r[0];
-      r[0] = cx<F>{z.x + z.y, F(0)};
-      r[LX] = cx<F>{z.x - z.y, F(0)};
-    } else if (2 * k == LX) {
-      r[k] = conj(r[k]);
-    } else {
-      const cx<F> A = r[k], B = conj(r[LX - k]);
-      const cx<F> E = scale(A + B, F(0.5));
-      const cx<F> O = muli<-1>(scale(A - B, F(0.5)));
-      const cx<F> WO = cmul(O, wpost[k]);
-      r[k] = E + WO;
-      r[LX - k] = conj(E - WO);
-    }
-  }
-}
-
-// Inverse of r2c_split up to a factor 2: slots 0..LX-1 receive Z' with
-// IFFT_{NX/2}(Z') = NX * x (unnormalised, like the full NX-point inverse).
-// The imaginary parts of the kx = 0 and kx = NX/2 bins are dropped.
-template <typename F, int NX, int NY, int BLOCK>
-__device__ __forceinline__ void c2r_split(cx<F>* lds, const cx<F>* __restrict__ wpost) {
-  constexpr int LX = NX / 2, NXH = LX + 1, NP = LX / 2 + 1;
-  for (int task = threadIdx.x; task < NY * NP; task += BLOCK) {
-    const int row = task / NP, k = task - row * NP;
-    cx<F>* r = lds + row * NXH;
-    if (k == 0) {
-      const F a = r[0].x, b = r[LX].x;
-      r[0] = cx<F>{a + b, a - b};
-    } else if (2 * k == LX) {
-      r[k] = scale(conj(r[k]), F(2));
-    } else {
-      const cx<F> X1 = r[k], X2 = conj(r[LX - k]);
-      const cx<F> Fe = X1 + X2;
-      const cx<F> Fo = cmulc(X1 - X2, wpost[k]);
-      r[k] = Fe + muli<+1>(Fo);
-      r[LX - k] = conj(Fe) + muli<+1>(conj(Fo));
-    }
-  }
-}
-
-constexpr int plane_block(int nx, int mode) { return (mode == PM_TAIL && nx >= 96) ? 512 : 256; }
-
 // ------------------------------------------------------------------ plane pass
-template <typename F, int NX, int NY, int MODE>
-__global__ __launch_bounds__(plane_block(NX, MODE)) void plane_kernel(PlaneArgs a) {
-  constexpr int BLOCK = plane_block(NX, MODE);
-  constexpr int LX = NX / 2, NXH = LX + 1;
+// One work-group per (z-plane, state).  The plane lives in LDS as
+// Z[y][k], k = 0..NX/2-1, the NX/2-point complex FFTs of the packed rows
+// x[2k] + i x[2k+1].  The real-to-half-spectrum split
+//   X[k] = (Z[k] + conj Z[NX/2-k])/2 - i W^k (Z[k] - conj Z[NX/2-k])/2,  W = exp(-2 pi i/NX)
+// is fused into the y-column phase: column FFT f (f = 0..NX/2-1) is carried by
+// TY threads; f = 2g + h with g >= 1 handles kx = g (h = 0) or kx = NX/2-g
+// (h = 1), so the two columns a split couples sit in neighbouring lanes.  f = 0
+// carries kx = 0 and kx = NX/2 packed as one complex column (both real along
+// y), f = 1 carries kx = NX/4.  That is NX/2 column FFTs for NX/2+1 columns,
+// done in a single round.
+__host__ __device__ constexpr int round64(int x) { return (x + 63) / 64 * 64; }
+template <int NX>
+struct PlaneShape {
+  static constexpr int LX = NX / 2;
+  static constexpr int COLT = LX * Plan<NX>::T;            // column-phase thread tasks (NY == NX)
+  static constexpr int BLOCK = round64(COLT) > 1024 ? 1024 : (round64(COLT) < 64 ? 64 : round64(COLT));
+};
+// Waves per SIMD that the LDS footprint admits (2 work-groups per CU for a
+// float32 128^2 plane): the register budget is capped to match, so that one
+// work-group's loads overlap another's LDS work.
+template <typename F, int NX>
+struct PlaneOcc {
+  static constexpr int LDS = NX * (NX / 2 + 1) * 2 * (int)sizeof(F);
+  static constexpr int WG = (160 * 1024 / LDS) < 1 ? 1 : (160 * 1024 / LDS);
+  static constexpr int W = WG * (PlaneShape<NX>::BLOCK / 64) / 4;
+  static constexpr int value = W < 1 ? 1 : (W > 8 ? 8 : W);
+};
+
+template <typename F, int NX, int MODE>
+struct PlaneWaves {
+  static constexpr int one_wg = (PlaneShape<NX>::BLOCK / 64 + 3) / 4;
+  static constexpr int value = MODE == PM_TAIL ? one_wg : PlaneOcc<F, NX>::value;
+};
+
+template <typename F, int NX, int MODE>
+__global__ __launch_bounds__(PlaneShape<NX>::BLOCK) __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE>::value)))
+void plane_kernel(PlaneArgs a) {
+  constexpr int NY = NX;
+  constexpr int BLOCK = PlaneShape<NX>::BLOCK;
+  constexpr int LX = NX / 2, NXH = LX + 1, HALF = LX / 2;
   using PX = Plan<LX>;
   using PY = Plan<NY>;
   constexpr int TX = PX::T, EX = PX::E, TY = PY::T, EY = PY::E;
-  constexpr int RPR = BLOCK / TX;                 // rows per round
-  constexpr int XR = (NY + RPR - 1) / RPR;        // row rounds
-  constexpr int CPR = BLOCK / TY;                 // columns per round
-  constexpr int YR = (NXH + CPR - 1) / CPR;       // column rounds
-  static_assert(BLOCK % TX == 0 && BLOCK % TY == 0, "block must hold whole transforms");
+  constexpr int NCF = LX;                          // column FFTs
+  constexpr int RPR = BLOCK / TX;                  // rows per round
+  constexpr int XR = (NY + RPR - 1) / RPR;         // row rounds
+  constexpr int SROW = NXH;                        // LDS row stride (complex)
+  static_assert(BLOCK % TX == 0, "block must hold whole row transforms");
+  static_assert(NCF * TY <= BLOCK, "one column round");
+  static_assert(NCF % 2 == 0, "column pairs");
 
-  __shared__ cx<F> lds[NY * NXH];
+  __shared__ cx<F> lds[NY * SROW];
 
   const int tid = threadIdx.x;
   const int z = blockIdx.x;
@@ -102,52 +88,111 @@ __global__ __launch_bounds__(plane_block(NX, MODE)) void plane_kernel(PlaneArgs 
 
   const cx<F>* rx = reinterpret_cast<const cx<F>*>(a.rx);
   const cx<F>* ry = reinterpret_cast<const cx<F>*>(a.ry);
-  const cx<F>* wpost = reinterpret_cast<const cx<F>*>(a.wpost);
+  const cx<F>* wpost = reinterpret_cast<const cx<F>*>(a.wpost);   // W^k, k = 0..NX/4
 
-  const int tx = tid % TX, rloc = tid / TX;      // row-phase lane / row slot
-  const int cl = tid % CPR, ty = tid / CPR;      // column-phase column slot / lane
+  // row phase mapping
+  const int tx = tid % TX, rloc = tid / TX;
+  // column phase mapping
+  const int f = tid % NCF, ty = tid / NCF;
+  const bool cact = ty < TY;                       // threads beyond NCF*TY idle in the column phase
+  const int g = f >> 1, h = f & 1;
+  const bool packed = (g == 0 && h == 0);
+  const int col = (g == 0) ? (h ? HALF : 0) : (h ? LX - g : g);   // LDS / spectrum column
+  const int tyc = cact ? ty : 0;
+  auto cbuf = [&](int i) { return &lds[i * SROW + col]; };
 
-  // ---------------- spectrum in: inverse y per column, then the c2r split
-  // (PM_TAIL repeats this per chain inside its own loop)
-  auto column_inverse = [&](const cx<F>* __restrict__ spec) {
-    for (int cr = 0; cr < YR; ++cr) {
-      const int col = cr * CPR + cl;
-      const bool act = col < NXH;
-      const int colc = act ? col : 0;
-      cx<F> v[EY];
-      if (act) {
-#pragma unroll
-        for (int m = 0; m < EY; ++m) v[m] = spec[(long)(ty + TY * m) * NXH + col];
-      }
-      fft<NY, +1>(v, ty, act, [&](int i) { return &lds[i * NXH + colc]; }, ry);
-      if (act) {
-#pragma unroll
-        for (int m = 0; m < EY; ++m) lds[(ty + TY * m) * NXH + col] = v[m];
-      }
-    }
-    __syncthreads();
-    c2r_split<F, NX, NY, BLOCK>(lds, wpost);
-    __syncthreads();
+  // W^k for k = 0..LX (W^(LX-j) = -conj W^j)
+  auto wk = [&](int k) -> cx<F> {
+    return k <= HALF ? wpost[k] : cx<F>{-wpost[LX - k].x, wpost[LX - k].y};
   };
 
-  // ---------------- columns forward out: r2c split, forward y per column, store
+  // ---- spectrum in: column loads (issued early when pipelined), inverse y FFT,
+  //      c2r split in registers, Z rows to LDS
+  auto column_load = [&](const cx<F>* __restrict__ spec, cx<F>* v) {
+    if (cact) {
+#pragma unroll
+      for (int m = 0; m < EY; ++m) {
+        const long o = (long)(tyc + TY * m) * NXH;
+        if (packed) {
+          const cx<F> y0 = spec[o], yl = spec[o + LX];
+          v[m] = cx<F>{y0.x - yl.y, y0.y + yl.x};            // Y0 + i Y_LX
+        } else {
+          v[m] = spec[o + col];
+        }
+      }
+    }
+  };
+  auto column_inverse_regs = [&](cx<F>* v) {
+    fft<NY, +1>(v, tyc, cact, cbuf, ry);
+    // split: needs X[LX - col] at the same y, held by the neighbouring lane
+    const cx<F> w = wk(col);
+#pragma unroll
+    for (int m = 0; m < EY; ++m) {
+      const cx<F> pr{__shfl_xor(v[m].x, 1), __shfl_xor(v[m].y, 1)};
+      cx<F> zv;
+      if (packed) {
+        zv = cx<F>{v[m].x + v[m].y, v[m].x - v[m].y};         // X0 = Re, X_LX = Im
+      } else if (col == HALF) {
+        zv = scale(conj(v[m]), F(2));
+      } else {
+        const cx<F> X2 = conj(pr);
+        const cx<F> Fe = v[m] + X2;
+        const cx<F> Fo = cmulc(v[m] - X2, w);
+        zv = Fe + muli<+1>(Fo);
+      }
+      v[m] = zv;
+    }
+    if (cact) {
+#pragma unroll
+      for (int m = 0; m < EY; ++m) lds[(tyc + TY * m) * SROW + col] = v[m];
+    }
+    __syncthreads();
+  };
+  auto column_inverse = [&](const cx<F>* __restrict__ spec) {
+    cx<F> v[EY];
+    column_load(spec, v);
+    column_inverse_regs(v);
+  };
+
+  // ---- columns forward out: r2c split on load, forward y FFT, store
   auto column_forward_store = [&](cx<F>* __restrict__ spec) {
     __syncthreads();
-    r2c_split<F, NX, NY, BLOCK>(lds, wpost);
-    __syncthreads();
-    for (int cr = 0; cr < YR; ++cr) {
-      const int col = cr * CPR + cl;
-      const bool act = col < NXH;
-      const int colc = act ? col : 0;
-      cx<F> v[EY];
-      if (act) {
+    cx<F> v[EY];
+    if (cact) {
+      const cx<F> w = wk(col);
 #pragma unroll
-        for (int m = 0; m < EY; ++m) v[m] = lds[(ty + TY * m) * NXH + col];
+      for (int m = 0; m < EY; ++m) {
+        const cx<F>* r = lds + (tyc + TY * m) * SROW;
+        if (packed) {
+          const cx<F> z0 = r[0];
+          v[m] = cx<F>{z0.x + z0.y, z0.x - z0.y};             // X0 + i X_LX (both real)
+        } else {
+          const cx<F> A = r[col], B = conj(r[LX - col]);
+          const cx<F> E = scale(A + B, F(0.5));
+          const cx<F> O = muli<-1>(scale(A - B, F(0.5)));
+          v[m] = E + cmul(O, w);
+        }
       }
-      fft<NY, -1>(v, ty, act, [&](int i) { return &lds[i * NXH + colc]; }, ry);
-      if (act) {
+    }
+    __syncthreads();   // every Z value read before the exchanges reuse the columns
+    fft<NY, -1>(v, tyc, cact, cbuf, ry);
+    if (cact && !packed) {
 #pragma unroll
-        for (int m = 0; m < EY; ++m) spec[(long)(ty + TY * m) * NXH + col] = v[m];
+      for (int m = 0; m < EY; ++m) spec[(long)(tyc + TY * m) * NXH + col] = v[m];
+    }
+    // unpack the DC / Nyquist column: X0[k] = (C[k] + conj C[-k])/2, X_LX[k] = -i (C[k] - conj C[-k])/2
+    if (cact && packed) {
+#pragma unroll
+      for (int m = 0; m < EY; ++m) lds[(tyc + TY * m) * SROW] = v[m];
+    }
+    __syncthreads();
+    if (cact && packed) {
+#pragma unroll
+      for (int m = 0; m < EY; ++m) {
+        const int ky = tyc + TY * m;
+        const cx<F> c = v[m], cm = conj(lds[((NY - ky) % NY) * SROW]);
+        spec[(long)ky * NXH] = scale(c + cm, F(0.5));
+        spec[(long)ky * NXH + LX] = muli<-1>(scale(c - cm, F(0.5)));
       }
     }
   };
@@ -155,6 +200,7 @@ __global__ __launch_bounds__(plane_block(NX, MODE)) void plane_kernel(PlaneArgs 
   if constexpr (MODE == PM_FWD) {
     const F* __restrict__ src = reinterpret_cast<const F*>(a.real_in) + real_off;
     const F* __restrict__ fac = a.fac ? reinterpret_cast<const F*>(a.fac) + fac_off : nullptr;
+#pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
       const bool act = row < NY;
@@ -168,45 +214,47 @@ __global__ __launch_bounds__(plane_block(NX, MODE)) void plane_kernel(PlaneArgs 
           const cx<F>* f2 = reinterpret_cast<const cx<F>*>(fac + (long)row * NX);
 #pragma unroll
           for (int m = 0; m < EX; ++m) {
-            const cx<F> f = f2[tx + TX * m];
-            v[m].x *= f.x;
-            v[m].y *= f.y;
+            const cx<F> fv = f2[tx + TX * m];
+            v[m].x *= fv.x;
+            v[m].y *= fv.y;
           }
         }
       }
-      fft<LX, -1>(v, tx, act, [&](int i) { return &lds[rowc * NXH + i]; }, rx);
+      fft<LX, -1>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
       if (act) {
 #pragma unroll
-        for (int m = 0; m < EX; ++m) lds[row * NXH + tx + TX * m] = v[m];
+        for (int m = 0; m < EX; ++m) lds[row * SROW + tx + TX * m] = v[m];
       }
     }
     column_forward_store(reinterpret_cast<cx<F>*>(a.spec_out) + spec_off);
   } else if constexpr (MODE == PM_LINK) {
     column_inverse(reinterpret_cast<const cx<F>*>(a.spec_in) + spec_off);
     const F* __restrict__ fac = reinterpret_cast<const F*>(a.fac) + fac_off;
+#pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
       const bool act = row < NY;
       const int rowc = act ? row : 0;
       cx<F> v[EX];
-      if (act) {
-#pragma unroll
-        for (int m = 0; m < EX; ++m) v[m] = lds[row * NXH + tx + TX * m];
-      }
-      fft<LX, +1>(v, tx, act, [&](int i) { return &lds[rowc * NXH + i]; }, rx);
+      cx<F> fv[EX];
       if (act) {
         const cx<F>* f2 = reinterpret_cast<const cx<F>*>(fac + (long)row * NX);
 #pragma unroll
         for (int m = 0; m < EX; ++m) {
-          const cx<F> f = f2[tx + TX * m];
-          v[m].x *= f.x;
-          v[m].y *= f.y;
+          v[m] = lds[row * SROW + tx + TX * m];
+          fv[m] = f2[tx + TX * m];
         }
       }
-      fft<LX, -1>(v, tx, act, [&](int i) { return &lds[rowc * NXH + i]; }, rx);
+      fft<LX, +1>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
+#pragma unroll
+      for (int m = 0; m < EX; ++m) {
+        v[m].x *= fv[m].x;
+        v[m].y *= fv[m].y;
+      }
+      fft<LX, -1>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
       if (act) {
 #pragma unroll
-        for (int m = 0; m < EX; ++m) lds[row * NXH + tx + TX * m] = v[m];
+        for (int m = 0; m < EX; ++m) lds[row * SROW + tx + TX * m] = v[m];
       }
     }
     column_forward_store(reinterpret_cast<cx<F>*>(a.spec_out) + spec_off);
@@ -216,11 +264,21 @@ __global__ __launch_bounds__(plane_block(NX, MODE)) void plane_kernel(PlaneArgs 
     for (int rr = 0; rr < XR; ++rr)
 #pragma unroll
       for (int m = 0; m < EX; ++m) acc[rr][m][0] = acc[rr][m][1] = 0.0;
+    // the next chain's column loads are issued before this chain's row work,
+    // so their latency hides behind it (one work-group per CU here)
+    const cx<F>* spec0 = reinterpret_cast<const cx<F>*>(a.spec_in) + spec_off;
+    cx<F> vc[EY];
+    column_load(spec0, vc);
     for (int k = 0; k < a.K; ++k) {
-      const cx<F>* spec = reinterpret_cast<const cx<F>*>(a.spec_in) + spec_off + (long)k * a.chain_stride;
       const F* __restrict__ fac = reinterpret_cast<const F*>(a.fac) + (long)(2 * k + 1) * a.fac_table_stride + fac_off;
       const double ck = a.coef[k];
-      column_inverse(spec);
+      column_inverse_regs(vc);
+      // (float64 planes have no registers to spare for the prefetch)
+      if (k + 1 < a.K) {
+        if constexpr (sizeof(F) == 4) {
+          column_load(spec0 + (long)(k + 1) * a.chain_stride, vc);
+        }
+      }
 #pragma unroll
       for (int rr = 0; rr < XR; ++rr) {
         const int row = rr * RPR + rloc;
@@ -229,20 +287,23 @@ __global__ __launch_bounds__(plane_block(NX, MODE)) void plane_kernel(PlaneArgs 
         cx<F> v[EX];
         if (act) {
 #pragma unroll
-          for (int m = 0; m < EX; ++m) v[m] = lds[row * NXH + tx + TX * m];
+          for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + tx + TX * m];
         }
-        fft<LX, +1>(v, tx, act, [&](int i) { return &lds[rowc * NXH + i]; }, rx);
+        fft<LX, +1>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
         if (act) {
           const cx<F>* f2 = reinterpret_cast<const cx<F>*>(fac + (long)row * NX);
 #pragma unroll
           for (int m = 0; m < EX; ++m) {
-            const cx<F> f = f2[tx + TX * m];
-            acc[rr][m][0] += ck * (double)(v[m].x * f.x);
-            acc[rr][m][1] += ck * (double)(v[m].y * f.y);
+            const cx<F> fv = f2[tx + TX * m];
+            acc[rr][m][0] += ck * (double)(v[m].x * fv.x);
+            acc[rr][m][1] += ck * (double)(v[m].y * fv.y);
           }
         }
       }
       __syncthreads();
+      if constexpr (sizeof(F) != 4) {
+        if (k + 1 < a.K) column_load(spec0 + (long)(k + 1) * a.chain_stride, vc);
+      }
     }
     F* __restrict__ dst = reinterpret_cast<F*>(a.real_out) + real_off;
 #pragma unroll
@@ -259,6 +320,7 @@ __global__ __launch_bounds__(plane_block(NX, MODE)) void plane_kernel(PlaneArgs 
     const F* __restrict__ phi = reinterpret_cast<const F*>(a.real_in) + real_off;
     const F* __restrict__ V = reinterpret_cast<const F*>(a.fac) + fac_off;
     F* __restrict__ dst = reinterpret_cast<F*>(a.real_out) + real_off;
+#pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
       const bool act = row < NY;
@@ -266,17 +328,17 @@ __global__ __launch_bounds__(plane_block(NX, MODE)) void plane_kernel(PlaneArgs 
       cx<F> v[EX];
       if (act) {
 #pragma unroll
-        for (int m = 0; m < EX; ++m) v[m] = lds[row * NXH + tx + TX * m];
+        for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + tx + TX * m];
       }
-      fft<LX, +1>(v, tx, act, [&](int i) { return &lds[rowc * NXH + i]; }, rx);
+      fft<LX, +1>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
       if (act) {
         const cx<F>* p2 = reinterpret_cast<const cx<F>*>(phi + (long)row * NX);
         const cx<F>* v2 = reinterpret_cast<const cx<F>*>(V + (long)row * NX);
         cx<F>* d2 = reinterpret_cast<cx<F>*>(dst + (long)row * NX);
 #pragma unroll
         for (int m = 0; m < EX; ++m) {
-          const cx<F> p = p2[tx + TX * m], w = v2[tx + TX * m];
-          d2[tx + TX * m] = cx<F>{v[m].x + w.x * p.x, v[m].y + w.y * p.y};
+          const cx<F> pv = p2[tx + TX * m], wv = v2[tx + TX * m];
+          d2[tx + TX * m] = cx<F>{v[m].x + wv.x * pv.x, v[m].y + wv.y * pv.y};
         }
       }
     }
@@ -338,21 +400,13 @@ __global__ __launch_bounds__(256) void pencil_kernel(PencilArgs a) {
 template <typename F, int N>
 static hipError_t launch_plane_n(int mode, const PlaneArgs& a, int nz, int nstates, hipStream_t st) {
   dim3 grid(nz, nstates);
+  dim3 block(PlaneShape<N>::BLOCK);
   switch (mode) {
-    case PM_FWD:
-      hipLaunchKernelGGL((plane_kernel<F, N, N, PM_FWD>), grid, dim3(plane_block(N, PM_FWD)), 0, st, a);
-      break;
-    case PM_LINK:
-      hipLaunchKernelGGL((plane_kernel<F, N, N, PM_LINK>), grid, dim3(plane_block(N, PM_LINK)), 0, st, a);
-      break;
-    case PM_TAIL:
-      hipLaunchKernelGGL((plane_kernel<F, N, N, PM_TAIL>), grid, dim3(plane_block(N, PM_TAIL)), 0, st, a);
-      break;
-    case PM_HTAIL:
-      hipLaunchKernelGGL((plane_kernel<F, N, N, PM_HTAIL>), grid, dim3(plane_block(N, PM_HTAIL)), 0, st, a);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case PM_FWD: hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD>), grid, block, 0, st, a); break;
+    case PM_LINK: hipLaunchKernelGGL((plane_kernel<F, N, PM_LINK>), grid, block, 0, st, a); break;
+    case PM_TAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_TAIL>), grid, block, 0, st, a); break;
+    case PM_HTAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_HTAIL>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -123,6 +123,9 @@ class Plan:
                                          _dptr(out["re"]), _dptr(out["re_perp"])))
         return out
 
+    def set_graph(self, on: bool):
+        self._check(self.lib.mpe_set_graph(self.h, 1 if on else 0))
+
     def set_states_per_launch(self, states: int):
         self._check(self.lib.mpe_set_states_per_launch(self.h, int(states)))
 
