@@ -144,6 +144,16 @@ mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh
  * the eager path. */
 mpe_status mpe_set_graph(mpe_plan p, int32_t on);
 
+/* Jacobi sweeps used by the last successful Rayleigh-Ritz solve of
+ * mpe_rayleigh_ritz / mpe_iterate (diagnostic; -1 if none). */
+int32_t mpe_last_jacobi_sweeps(mpe_plan p);
+
+/* Durations in microseconds of the phases of the last small dense solve
+ * (Cholesky, triangular solves, Jacobi sweeps, eigenvector rebuild, back
+ * substitution), from the GPU's constant clock; us must hold 5 doubles.
+ * Diagnostic: synchronises the plan's stream. */
+mpe_status mpe_small_dense_phases(mpe_plan p, double* us);
+
 /* Launch-shape knob: states per propagation launch (0 = all m). */
 mpe_status mpe_set_states_per_launch(mpe_plan p, int32_t states);
 
@@ -158,6 +168,43 @@ enum {
 };
 mpe_status mpe_profile_enable(mpe_plan p, int32_t on);
 mpe_status mpe_get_kernel_times(mpe_plan p, double* ms, int64_t* launches);
+
+/* ---------------------------------------------------------------------------
+ * Batched uneven systems: many independent eigenproblems (different grids,
+ * state counts and potentials, one order and precision) advanced together.
+ * Systems with the same grid share every propagation and H launch (one launch
+ * per pass over all their states); overlaps, the small dense solve and the
+ * rotation run per system; one iteration of all systems is one hipGraph
+ * replay.  Results equal those of separate plans bitwise.
+ * ------------------------------------------------------------------------- */
+typedef struct mpe_batch_s* mpe_batch;
+
+typedef struct {
+  int32_t grid[3];     /* as for mpe_plan_create                                  */
+  double box[3];
+  int32_t n_states;
+  int32_t n_guard;
+  const double* V;     /* device float64 [nz][ny][nx]; copied at creation          */
+} mpe_system_desc;
+
+/* Create plans for `count` systems on one stream.  Errors as mpe_plan_create. */
+mpe_status mpe_batch_create(mpe_batch* out, int32_t count, const mpe_system_desc* systems, int32_t order,
+                            mpe_precision prec, double hbar2_over_m, void* hip_stream);
+mpe_status mpe_batch_destroy(mpe_batch b);
+const char* mpe_batch_last_error(mpe_batch b);
+
+/* psi[i] <- T_order(dt) psi[i] for every system (psi: `count` device state
+ * blocks, each [m_i][nz][ny][nx]). */
+mpe_status mpe_batch_step(mpe_batch b, void* const* psi, double dt);
+
+/* One fused iteration (as mpe_iterate) of every system.  Host outputs hold
+ * sum_i m_i doubles, system i's values at offset sum_{k<i} m_k; any may be
+ * NULL.  The first failing system's status is returned (others still ran). */
+mpe_status mpe_batch_iterate(mpe_batch b, void* const* psi, double dt, double* eig, double* rh, double* re,
+                             double* re_perp);
+
+/* Kernel launches in the captured iteration graph (diagnostic). */
+int32_t mpe_batch_launches_per_step(mpe_batch b);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,12 @@ _dp = C.POINTER(C.c_double)
 _vp = C.c_void_p
 _i32 = C.c_int32
 
+class SystemDesc(C.Structure):
+    """mpe_system_desc of include/mpe.h."""
+    _fields_ = [("grid", C.c_int32 * 3), ("box", C.c_double * 3), ("n_states", C.c_int32),
+                ("n_guard", C.c_int32), ("V", C.c_void_p)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "mpe_abi_version": (C.c_int, []),
@@ -44,8 +50,16 @@ SIGNATURES = {
     "mpe_iterate": (C.c_int, [_vp, _vp, C.c_double, _dp, _dp, _dp, _dp]),
     "mpe_set_states_per_launch": (C.c_int, [_vp, _i32]),
     "mpe_set_graph": (C.c_int, [_vp, _i32]),
+    "mpe_last_jacobi_sweeps": (C.c_int32, [_vp]),
+    "mpe_small_dense_phases": (C.c_int, [_vp, _dp]),
     "mpe_profile_enable": (C.c_int, [_vp, _i32]),
     "mpe_get_kernel_times": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64)]),
+    "mpe_batch_create": (C.c_int, [C.POINTER(_vp), _i32, C.POINTER(SystemDesc), _i32, C.c_int, C.c_double, _vp]),
+    "mpe_batch_destroy": (C.c_int, [_vp]),
+    "mpe_batch_last_error": (C.c_char_p, [_vp]),
+    "mpe_batch_step": (C.c_int, [_vp, C.POINTER(_vp), C.c_double]),
+    "mpe_batch_iterate": (C.c_int, [_vp, C.POINTER(_vp), C.c_double, _dp, _dp, _dp, _dp]),
+    "mpe_batch_launches_per_step": (C.c_int32, [_vp]),
 }
 
 

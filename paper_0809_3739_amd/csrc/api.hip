@@ -143,13 +143,14 @@ struct mpe_plan_s {
   double* partials = nullptr;  // gram / residual partials
   size_t partials_bytes = 0;
   double* mats = nullptr;      // S, Hs, M, L, C (mp x mp each)
-  double* rot = nullptr;       // Jacobi rotation log
+  double* rot = nullptr;       // Jacobi eigenvector accumulator U (mp x mp)
   size_t rot_count = 0;
   double* res = nullptr;       // theta | rh | re | re_perp (MAXM each) | scratch (2 MAXM) | status
   int* status = nullptr;
   double* host_res = nullptr;  // pinned mirror of res + status
   size_t res_bytes = 0;
   int64_t ws_bytes = 0;
+  long long* ticks = nullptr;  // small-dense phase stamps (device, 8 entries; diagnostics)
 
   bool have_v = false;
   double h2m = 1.0;
@@ -290,6 +291,8 @@ PlaneArgs plane_base(mpe_plan p) {
   a.wpost = p->wpost();
   a.real_state_stride = p->N;
   a.spec_state_stride = p->spec;
+  a.fac_table_stride = p->N;
+  a.fac_index = -1;
   return a;
 }
 
@@ -298,13 +301,11 @@ PencilArgs pencil_base(mpe_plan p, void* data, const void* tab) {
   std::memset(&a, 0, sizeof(a));
   a.data = data;
   a.rz = p->rz();
-  const size_t f = p->fsz;
-  a.tx = tab;
-  a.ty = (const char*)tab + f * p->nxh;
-  a.tz = (const char*)tab + f * (p->nxh + p->ny);
+  a.tab = tab;
   a.state_stride = p->spec;
   a.M = (int)p->M;
   a.NXH = p->nxh;
+  a.NY = p->ny;
   return a;
 }
 
@@ -319,16 +320,17 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
   mpe_coeffs(p->K, c);
   for (int k = 1; k <= p->K; ++k) {
     void* Wk = chain_spec(p, k - 1);
-    const void* half = (const char*)p->fac + (size_t)(2 * k - 1) * p->N * f;  // exp(-dt V / 2k)
-    const void* full = (const char*)p->fac + (size_t)(k - 1) * p->N * f;      // exp(-dt V / k)
+    const int half = 2 * k - 1;   // table exp(-dt V / 2k)
+    const int full = k - 1;       // table exp(-dt V / k)
     const void* ktab = (const char*)p->kin + (size_t)(k - 1) * (p->nxh + p->ny + p->nz) * f;
     Timer t;
     tic(p, t, MPE_KC_PLANE_FWD);
     HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
              PlaneArgs a = plane_base(p);
              a.real_in = src;
-             a.fac = half;
-             a.spec_out = Wk;
+             a.fac = p->fac;
+             a.fac_index = half;
+             a.spec = Wk;
              a.state0 = s0;
              return launch_plane(p->dbl, PM_FWD, p->nx, a, p->nz, cnt, p->st);
            }));
@@ -345,9 +347,9 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
         tic(p, t, MPE_KC_PLANE_LINK);
         HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
                  PlaneArgs a = plane_base(p);
-                 a.spec_in = Wk;
-                 a.spec_out = Wk;
-                 a.fac = full;
+                 a.spec = Wk;
+                 a.fac = p->fac;
+                 a.fac_index = full;
                  a.state0 = s0;
                  return launch_plane(p->dbl, PM_LINK, p->nx, a, p->nz, cnt, p->st);
                }));
@@ -359,10 +361,9 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
   tic(p, t, MPE_KC_PLANE_TAIL);
   HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
            PlaneArgs a = plane_base(p);
-           a.spec_in = chain_spec(p, 0);
+           a.spec = chain_spec(p, 0);
            a.chain_stride = (long)p->m * p->spec;
            a.fac = p->fac;
-           a.fac_table_stride = p->N;
            a.real_out = dst;
            a.K = p->K;
            for (int k = 0; k < p->K; ++k) a.coef[k] = c[k];
@@ -395,7 +396,8 @@ mpe_status run_h(mpe_plan p, const void* src, void* hdst) {
            PlaneArgs a = plane_base(p);
            a.real_in = src;
            a.fac = nullptr;
-           a.spec_out = Wh;
+           a.fac_index = -1;
+           a.spec = Wh;
            a.state0 = s0;
            hipError_t e = launch_plane(p->dbl, PM_FWD, p->nx, a, p->nz, cnt, p->st);
            if (e != hipSuccess) return e;
@@ -404,7 +406,7 @@ mpe_status run_h(mpe_plan p, const void* src, void* hdst) {
            e = launch_pencil(p->dbl, PK_ADD, p->nz, b, cnt, p->st);
            if (e != hipSuccess) return e;
            PlaneArgs c = plane_base(p);
-           c.spec_in = Wh;
+           c.spec = Wh;
            c.real_in = src;
            c.fac = p->Vf;
            c.real_out = hdst;
@@ -471,6 +473,7 @@ mpe_status run_small_dense(mpe_plan p, int mode) {
   d.mp = p->mp;
   d.mode = mode;
   d.max_sweeps = p->max_sweeps;
+  d.ticks = p->ticks;
   d.tol = p->jacobi_tol;
   d.pivot_tol = p->pivot_tol;
   Timer t;
@@ -657,7 +660,7 @@ mpe_status mpe_plan_destroy(mpe_plan p) {
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->gst) (void)hipStreamDestroy(p->gst);
   void* bufs[] = {p->W, p->phi, p->hphi, p->V64, p->Vf, p->fac, p->kin, p->hk, p->roots,
-                  p->partials, p->mats, p->rot, p->res};
+                  p->partials, p->mats, p->rot, p->res, p->ticks};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (p->host_res) (void)hipHostFree(p->host_res);
@@ -718,8 +721,7 @@ mpe_status mpe_plan_create(mpe_plan* out, const int32_t grid[3], const double bo
   long rch;
   const int nrch = rot_chunks(p, &rch);
   p->partials_bytes = std::max((size_t)3 * ngch * p->mp * p->mp, (size_t)nrch * p->mp) * sizeof(double);
-  const int nn = (m + 1) & ~1;
-  p->rot_count = (size_t)(p->max_sweeps + 1) * (nn - 1) * (nn / 2) + 16;
+  p->rot_count = (size_t)p->mp * p->mp / 4 + 4;   // U of the Jacobi solver: mp x mp doubles
   p->res_bytes = 6 * MAXM * sizeof(double) + 4 * sizeof(int);
   const int tablen = p->nxh + p->ny + p->nz;
   std::vector<double> r;
@@ -743,7 +745,8 @@ mpe_status mpe_plan_create(mpe_plan* out, const int32_t grid[3], const double bo
             alloc(&p->kin, (size_t)p->K * tablen * f) && alloc(&p->hk, (size_t)tablen * f) &&
             alloc(&p->roots, r.size() / 2 * cxs) && alloc((void**)&p->partials, p->partials_bytes) &&
             alloc((void**)&p->mats, 5 * (size_t)p->mp * p->mp * sizeof(double)) &&
-            alloc((void**)&p->rot, p->rot_count * 4 * sizeof(double)) && alloc((void**)&p->res, p->res_bytes);
+            alloc((void**)&p->rot, p->rot_count * 4 * sizeof(double)) && alloc((void**)&p->res, p->res_bytes) &&
+            alloc((void**)&p->ticks, 8 * sizeof(long long));
   if (!ok) {
     mpe_plan_destroy(p);
     return MPE_ERR_OUT_OF_MEMORY;
@@ -923,6 +926,21 @@ mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh
   return finish_iterate(p, psi, eig, rh, re, re_perp);
 }
 
+mpe_status mpe_small_dense_phases(mpe_plan p, double* us) {
+  if (!p || !us) return MPE_ERR_INVALID_ARGUMENT;
+  long long t[8];
+  HIPCHK(p, hipStreamSynchronize(p->st));
+  HIPCHK(p, hipMemcpy(t, p->ticks, sizeof t, hipMemcpyDeviceToHost));
+  for (int i = 0; i < 5; ++i) us[i] = (double)(t[i + 1] - t[i]) / 100.0;   // 100 MHz clock
+  return MPE_OK;
+}
+
+int32_t mpe_last_jacobi_sweeps(mpe_plan p) {
+  if (!p || !p->host_res) return -1;
+  const int* hs = reinterpret_cast<const int*>(p->host_res + 6 * MAXM);
+  return hs[0] == ST_OK ? hs[1] : -1;
+}
+
 mpe_status mpe_set_graph(mpe_plan p, int32_t on) {
   if (!p) return MPE_ERR_INVALID_ARGUMENT;
   p->use_graph = on != 0;
@@ -954,6 +972,345 @@ mpe_status mpe_get_kernel_times(mpe_plan p, double* ms, int64_t* launches) {
     p->kcount[i] = 0;
   }
   return MPE_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched uneven systems
+// Systems are grouped by grid.  Every propagation and H pass of a group is one
+// launch over all states of all its systems: the kernels read each state's
+// addresses (its system's spectra, tables and potential) from a descriptor
+// table.  Overlaps, the small dense solve and the rotation run per system.
+// The whole iteration for every system is captured as one hipGraph.
+namespace {
+
+struct BatchGroup {
+  int nx = 0, ny = 0, nz = 0;
+  std::vector<int> sys;            // plan indices
+  int nstates = 0;
+  StateDesc* d_step = nullptr;     // device descriptors: propagation (psi -> phi)
+  StateDesc* d_h = nullptr;        // device descriptors: H (phi -> hphi)
+  std::vector<StateDesc> h_step, h_h;
+};
+
+}  // namespace
+
+struct mpe_batch_s {
+  int count = 0, K = 0, dbl = 0;
+  hipStream_t st = nullptr;
+  std::string err;
+  std::vector<mpe_plan> plans;
+  std::vector<BatchGroup> groups;
+  hipStream_t gst = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<void*> g_psi;
+  hipEvent_t ev_in = nullptr;
+  int launches = 0;
+};
+
+namespace {
+
+mpe_status bfail(mpe_batch b, mpe_status s, const std::string& msg) {
+  if (b) b->err = msg;
+  return s;
+}
+
+#define BHIPCHK(b, expr)                                                                          \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return bfail(b, MPE_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+void batch_drop_graph(mpe_batch b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->g_psi.clear();
+}
+
+// Descriptors of one group for the given state blocks.
+void fill_descs(mpe_batch b, BatchGroup& g, void* const* psi, bool step_inplace) {
+  g.h_step.clear();
+  g.h_h.clear();
+  for (int si : g.sys) {
+    mpe_plan p = b->plans[si];
+    const size_t rs = (size_t)p->N * p->fsz, ss = (size_t)p->spec * p->cx_size();
+    for (int j = 0; j < p->m; ++j) {
+      StateDesc d;
+      d.real_in = (const char*)psi[si] + j * rs;
+      d.real_out = step_inplace ? (char*)psi[si] + j * rs : (char*)p->phi + j * rs;
+      d.spec = (char*)p->W + j * ss;
+      d.fac = p->fac;
+      d.V = p->Vf;
+      d.kin = p->kin;
+      d.hk = p->hk;
+      d.chain_stride = (long)p->m * p->spec;
+      g.h_step.push_back(d);
+      StateDesc e = d;
+      e.real_in = (const char*)p->phi + j * rs;
+      e.real_out = (char*)p->hphi + j * rs;
+      g.h_h.push_back(e);
+    }
+  }
+}
+
+mpe_status upload_descs(mpe_batch b) {
+  for (auto& g : b->groups) {
+    BHIPCHK(b, hipMemcpyAsync(g.d_step, g.h_step.data(), g.h_step.size() * sizeof(StateDesc), hipMemcpyHostToDevice,
+                              b->st));
+    BHIPCHK(b, hipMemcpyAsync(g.d_h, g.h_h.data(), g.h_h.size() * sizeof(StateDesc), hipMemcpyHostToDevice, b->st));
+  }
+  BHIPCHK(b, hipStreamSynchronize(b->st));   // host vectors may change after this call
+  return MPE_OK;
+}
+
+// Propagation of every state of the group: phi (or psi in place) <- T_2K psi.
+mpe_status enqueue_group_step(mpe_batch b, BatchGroup& g, hipStream_t st) {
+  mpe_plan p0 = b->plans[g.sys[0]];
+  double c[MAX_K];
+  mpe_coeffs(b->K, c);
+  for (int k = 1; k <= b->K; ++k) {
+    PlaneArgs a = plane_base(p0);
+    a.desc = g.d_step;
+    a.chain = k - 1;
+    a.fac_index = 2 * k - 1;
+    BHIPCHK(b, launch_plane(b->dbl, PM_FWD, g.nx, a, g.nz, g.nstates, st));
+    ++b->launches;
+    for (int l = 1; l <= k; ++l) {
+      PencilArgs pa = pencil_base(p0, nullptr, nullptr);
+      pa.desc = g.d_step;
+      pa.chain = k - 1;
+      pa.desc_tables = 0;
+      BHIPCHK(b, launch_pencil(b->dbl, PK_EXP, g.nz, pa, g.nstates, st));
+      ++b->launches;
+      if (l < k) {
+        PlaneArgs la = plane_base(p0);
+        la.desc = g.d_step;
+        la.chain = k - 1;
+        la.fac_index = k - 1;
+        BHIPCHK(b, launch_plane(b->dbl, PM_LINK, g.nx, la, g.nz, g.nstates, st));
+        ++b->launches;
+      }
+    }
+  }
+  PlaneArgs t = plane_base(p0);
+  t.desc = g.d_step;
+  t.chain = 0;
+  t.K = b->K;
+  for (int k = 0; k < b->K; ++k) t.coef[k] = c[k];
+  BHIPCHK(b, launch_plane(b->dbl, PM_TAIL, g.nx, t, g.nz, g.nstates, st));
+  ++b->launches;
+  return MPE_OK;
+}
+
+mpe_status enqueue_group_h(mpe_batch b, BatchGroup& g, hipStream_t st) {
+  mpe_plan p0 = b->plans[g.sys[0]];
+  PlaneArgs a = plane_base(p0);
+  a.desc = g.d_h;
+  a.chain = 0;
+  a.fac_index = -1;
+  BHIPCHK(b, launch_plane(b->dbl, PM_FWD, g.nx, a, g.nz, g.nstates, st));
+  PencilArgs pa = pencil_base(p0, nullptr, nullptr);
+  pa.desc = g.d_h;
+  pa.chain = 0;
+  pa.desc_tables = 1;
+  BHIPCHK(b, launch_pencil(b->dbl, PK_ADD, g.nz, pa, g.nstates, st));
+  PlaneArgs c = plane_base(p0);
+  c.desc = g.d_h;
+  c.chain = 0;
+  BHIPCHK(b, launch_plane(b->dbl, PM_HTAIL, g.nx, c, g.nz, g.nstates, st));
+  b->launches += 3;
+  return MPE_OK;
+}
+
+// All device work of one batched iteration on stream st (plans temporarily enqueue on st).
+mpe_status enqueue_batch_iterate(mpe_batch b, void* const* psi, hipStream_t st) {
+  b->launches = 0;
+  for (auto& g : b->groups) {
+    mpe_status s = enqueue_group_step(b, g, st);
+    if (s != MPE_OK) return s;
+  }
+  for (auto& g : b->groups) {
+    mpe_status s = enqueue_group_h(b, g, st);
+    if (s != MPE_OK) return s;
+  }
+  for (int i = 0; i < b->count; ++i) {
+    mpe_plan p = b->plans[i];
+    hipStream_t keep = p->st;
+    p->st = st;
+    const void* X[3] = {p->phi, p->phi, psi[i]};
+    const void* Y[3] = {p->phi, p->hphi, p->phi};
+    mpe_status s = run_gram(p, X, Y, 3, p->S());
+    if (s == MPE_OK) {
+      hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, p->re(), p->reperp(), st);
+      if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));
+    }
+    if (s == MPE_OK) s = run_small_dense(p, SD_RR);
+    if (s == MPE_OK) s = run_rotate(p, p->phi, p->hphi, psi[i], p->hphi);
+    if (s == MPE_OK) {
+      hipError_t e = hipMemcpyAsync(p->host_res, p->res, p->res_bytes, hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));
+    }
+    p->st = keep;
+    if (s != MPE_OK) return bfail(b, s, "system " + std::to_string(i) + ": " + p->err);
+    b->launches += 7;
+  }
+  return MPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpe_status mpe_batch_destroy(mpe_batch b) {
+  if (!b) return MPE_ERR_INVALID_ARGUMENT;
+  (void)hipStreamSynchronize(b->st);
+  batch_drop_graph(b);
+  for (auto& g : b->groups) {
+    if (g.d_step) (void)hipFree(g.d_step);
+    if (g.d_h) (void)hipFree(g.d_h);
+  }
+  for (auto p : b->plans)
+    if (p) mpe_plan_destroy(p);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->gst) (void)hipStreamDestroy(b->gst);
+  delete b;
+  return MPE_OK;
+}
+
+mpe_status mpe_batch_create(mpe_batch* out, int32_t count, const mpe_system_desc* systems, int32_t order,
+                            mpe_precision prec, double hbar2_over_m, void* hip_stream) {
+  if (!out) return MPE_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (count < 1 || !systems) return MPE_ERR_INVALID_ARGUMENT;
+  mpe_batch b = new mpe_batch_s();
+  b->count = count;
+  b->K = order / 2;
+  b->dbl = prec == MPE_FP64;
+  b->st = reinterpret_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < count; ++i) {
+    const mpe_system_desc& sd = systems[i];
+    mpe_plan p = nullptr;
+    mpe_status s = mpe_plan_create(&p, sd.grid, sd.box, sd.n_states, order, prec, sd.n_guard, hip_stream);
+    if (s != MPE_OK) {
+      mpe_batch_destroy(b);
+      return s;
+    }
+    b->plans.push_back(p);
+    s = mpe_set_potential(p, sd.V, hbar2_over_m);
+    if (s != MPE_OK) {
+      mpe_batch_destroy(b);
+      return s;
+    }
+    int gi = -1;
+    for (size_t k = 0; k < b->groups.size(); ++k)
+      if (b->groups[k].nx == p->nx && b->groups[k].ny == p->ny && b->groups[k].nz == p->nz) gi = (int)k;
+    if (gi < 0) {
+      BatchGroup g;
+      g.nx = p->nx;
+      g.ny = p->ny;
+      g.nz = p->nz;
+      b->groups.push_back(g);
+      gi = (int)b->groups.size() - 1;
+    }
+    b->groups[gi].sys.push_back(i);
+    b->groups[gi].nstates += p->m;
+  }
+  for (auto& g : b->groups) {
+    if (hipMalloc((void**)&g.d_step, g.nstates * sizeof(StateDesc)) != hipSuccess ||
+        hipMalloc((void**)&g.d_h, g.nstates * sizeof(StateDesc)) != hipSuccess) {
+      mpe_batch_destroy(b);
+      return MPE_ERR_OUT_OF_MEMORY;
+    }
+  }
+  if (hipStreamCreateWithFlags(&b->gst, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess) {
+    mpe_batch_destroy(b);
+    return MPE_ERR_DEVICE;
+  }
+  *out = b;
+  return MPE_OK;
+}
+
+const char* mpe_batch_last_error(mpe_batch b) { return b ? b->err.c_str() : "null batch"; }
+
+int32_t mpe_batch_launches_per_step(mpe_batch b) { return b ? b->launches : -1; }
+
+mpe_status mpe_batch_step(mpe_batch b, void* const* psi, double dt) {
+  if (!b || !psi) return MPE_ERR_INVALID_ARGUMENT;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return bfail(b, MPE_ERR_INVALID_ARGUMENT, "dt must be positive");
+  for (int i = 0; i < b->count; ++i) {
+    if (!psi[i]) return bfail(b, MPE_ERR_INVALID_ARGUMENT, "null state block");
+    mpe_plan p = b->plans[i];
+    p->rr_cache_psi = nullptr;
+    mpe_status s = ensure_tables(p, dt);
+    if (s != MPE_OK) return bfail(b, s, p->err);
+    p->last_dt = dt;
+  }
+  batch_drop_graph(b);   // descriptors are rewritten for the in-place step
+  for (auto& g : b->groups) fill_descs(b, g, psi, true);
+  mpe_status s = upload_descs(b);
+  if (s != MPE_OK) return s;
+  for (auto& g : b->groups) {
+    s = enqueue_group_step(b, g, b->st);
+    if (s != MPE_OK) return s;
+  }
+  BHIPCHK(b, hipStreamSynchronize(b->st));
+  return MPE_OK;
+}
+
+mpe_status mpe_batch_iterate(mpe_batch b, void* const* psi, double dt, double* eig, double* rh, double* re,
+                             double* re_perp) {
+  if (!b || !psi) return MPE_ERR_INVALID_ARGUMENT;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return bfail(b, MPE_ERR_INVALID_ARGUMENT, "dt must be positive");
+  bool same = b->gexec != nullptr && (int)b->g_psi.size() == b->count;
+  for (int i = 0; i < b->count; ++i) {
+    if (!psi[i]) return bfail(b, MPE_ERR_INVALID_ARGUMENT, "null state block");
+    if (same && b->g_psi[i] != psi[i]) same = false;
+    mpe_plan p = b->plans[i];
+    p->rr_cache_psi = nullptr;
+    mpe_status s = ensure_tables(p, dt);
+    if (s != MPE_OK) return bfail(b, s, p->err);
+    p->last_dt = dt;
+  }
+  if (!same) {
+    batch_drop_graph(b);
+    for (auto& g : b->groups) fill_descs(b, g, psi, false);
+    mpe_status s = upload_descs(b);
+    if (s != MPE_OK) return s;
+    BHIPCHK(b, hipStreamBeginCapture(b->gst, hipStreamCaptureModeRelaxed));
+    s = enqueue_batch_iterate(b, psi, b->gst);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->gst, &g);
+    if (s != MPE_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return bfail(b, MPE_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    b->graph = g;
+    BHIPCHK(b, hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+    b->g_psi.assign(psi, psi + b->count);
+  }
+  BHIPCHK(b, hipEventRecord(b->ev_in, b->st));
+  BHIPCHK(b, hipStreamWaitEvent(b->gst, b->ev_in, 0));
+  BHIPCHK(b, hipGraphLaunch(b->gexec, b->gst));
+  BHIPCHK(b, hipStreamSynchronize(b->gst));
+  long off = 0;
+  mpe_status first = MPE_OK;
+  for (int i = 0; i < b->count; ++i) {
+    mpe_plan p = b->plans[i];
+    mpe_status s = finish_iterate(p, psi[i], eig ? eig + off : nullptr, rh ? rh + off : nullptr,
+                                  re ? re + off : nullptr, re_perp ? re_perp + off : nullptr);
+    if (s != MPE_OK && first == MPE_OK) {
+      first = s;
+      b->err = "system " + std::to_string(i) + ": " + p->err;
+    }
+    off += p->m;
+  }
+  return first;
 }
 
 }  // extern "C"

@@ -195,7 +195,23 @@ __device__ __forceinline__ int out_index(int t, int q, int r) {
 // buf(i) addresses element i of this transform in LDS.  Every thread of the
 // work-group must call this (it contains barriers); it is bracketed by barriers
 // so the region may be read before and written after it without further sync.
-template <int L, int E, int T, int R, int NS, typename F, typename Addr>
+// Ordering point for an exchange whose lanes all sit in one wavefront: LDS
+// operations of a wavefront execute in program order, so only the compiler
+// must be kept from moving LDS accesses across it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <bool WAVE>
+__device__ __forceinline__ void xsync() {
+  if constexpr (WAVE) wave_sync();
+  else __syncthreads();
+}
+
+// WAVE = true: the T lanes of every transform are consecutive lanes of one
+// wavefront, so the exchange needs no work-group barrier.
+template <int L, int E, int T, int R, int NS, bool WAVE = false, typename F, typename Addr>
 __device__ __forceinline__ void exchange(cx<F>* v, int t, bool active, Addr buf) {
   constexpr int NB = E / R;
   if constexpr (T == 1) {
@@ -208,36 +224,36 @@ __device__ __forceinline__ void exchange(cx<F>* v, int t, bool active, Addr buf)
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = tmp[m];
   } else {
-    __syncthreads();
+    xsync<WAVE>();
     if (active) {
 #pragma unroll
       for (int q = 0; q < NB; ++q)
 #pragma unroll
         for (int r = 0; r < R; ++r) *buf(out_index<L, E, T, R, NS>(t, q, r)) = v[q + r * NB];
     }
-    __syncthreads();
+    xsync<WAVE>();
     if (active) {
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = *buf(t + T * m);
     }
-    __syncthreads();
+    xsync<WAVE>();
   }
 }
 
 // Full length-L transform of the values v[] (strided order in and out).
 // All threads of the work-group must call it together (barriers inside when
 // the transform spans several lanes).
-template <int L, int DIR, typename F, typename Addr>
+template <int L, int DIR, bool WAVE = false, typename F, typename Addr>
 __device__ __forceinline__ void fft(cx<F>* v, int t, bool active, Addr buf, const cx<F>* __restrict__ roots) {
   using P = Plan<L>;
   constexpr int E = P::E, T = P::T;
   stage<L, E, T, P::R0, 1, DIR>(v, t, roots);
   if constexpr (P::S >= 2) {
-    exchange<L, E, T, P::R0, 1>(v, t, active, buf);
+    exchange<L, E, T, P::R0, 1, WAVE>(v, t, active, buf);
     stage<L, E, T, P::R1, P::R0, DIR>(v, t, roots);
   }
   if constexpr (P::S >= 3) {
-    exchange<L, E, T, P::R1, P::R0>(v, t, active, buf);
+    exchange<L, E, T, P::R1, P::R0, WAVE>(v, t, active, buf);
     stage<L, E, T, P::R2, P::R0 * P::R1, DIR>(v, t, roots);
   }
 }

@@ -31,51 +31,98 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
 }
 
 // ------------------------------------------------------------------ Gram partials
-// Work-group: 256 threads (4 waves).  Output tiles of 16x16 over mp x mp are
-// dealt round-robin to the waves (<= 16 tiles each for mp <= 128).  Points are
-// staged through LDS in slabs of GSLAB, transposed to [point][state].
-constexpr int GSLAB = 16;
-constexpr int GMAXT = 16;
+// Work-group: 256 threads (4 waves).  The 16x16 output tiles of an mp x mp
+// product (NT = mp/16 per side, compile time) are dealt round-robin to the
+// waves; for X == Y (SYM) only tiles ti <= tj are formed and mirrored on
+// store.  Points are staged through LDS in slabs of GSLAB, transposed to
+// [point][state]; the next slab is loaded into registers while the MFMAs of
+// the current one run.
+constexpr int GSLAB = 32;
+constexpr int GLD = MAXM + 1;   // LDS row: consecutive points of a state land in distinct banks
 
-template <typename F>
+template <int NT, bool SYM>
+struct GramTiles {
+  static constexpr int count = SYM ? NT * (NT + 1) / 2 : NT * NT;
+  static constexpr int per_wave = (count + 3) / 4;
+};
+
+__device__ __forceinline__ void tile_coords(int u, int nt, bool sym, int& ti, int& tj) {
+  if (!sym) {
+    ti = u / nt;
+    tj = u - ti * nt;
+    return;
+  }
+  ti = 0;
+  while (u >= nt - ti) {
+    u -= nt - ti;
+    ++ti;
+  }
+  tj = ti + u;
+}
+
+template <typename F, int NT, bool SYM>
 __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
-  __shared__ double xs[GSLAB][MAXM + 2];
-  __shared__ double ys[GSLAB][MAXM + 2];
+  constexpr int mp = NT * 16;
+  constexpr int TPW = GramTiles<NT, SYM>::per_wave;
+  constexpr int NTILE = GramTiles<NT, SYM>::count;
+  constexpr int PER = (mp * GSLAB + 255) / 256;   // staged elements per thread and array
+  __shared__ double xs[GSLAB][GLD];
+  __shared__ double ys[SYM ? 1 : GSLAB][SYM ? 1 : GLD];
   const int prod = blockIdx.y;
   const F* __restrict__ X = reinterpret_cast<const F*>(g.X[prod]);
   const F* __restrict__ Y = reinterpret_cast<const F*>(g.Y[prod]);
-  const bool same = X == Y;
-  const int m = g.m, mp = g.mp, nt = mp / 16;
+  const int m = g.m;
   const long N = g.N;
   const long p_begin = (long)blockIdx.x * g.chunk;
   const long p_end = min(N, p_begin + g.chunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  d4 acc[GMAXT];
+  int tiv[TPW], tjv[TPW];
 #pragma unroll
-  for (int t = 0; t < GMAXT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < TPW; ++t) {
+    const int u = wave + 4 * t;
+    tile_coords(u < NTILE ? u : 0, NT, SYM, tiv[t], tjv[t]);
+  }
+  d4 acc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (long p0 = p_begin; p0 < p_end; p0 += GSLAB) {
-    // stage: element (state s, point p0 + q) -> xs[q][s]
-    for (int e = tid; e < mp * GSLAB; e += 256) {
-      const int s = e / GSLAB, q = e - s * GSLAB;
+  F px[PER], py[PER];
+  auto load = [&](long p0) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 256 * r;
+      const int st = e / GSLAB, q = e - st * GSLAB;
       const long p = p0 + q;
-      const bool ok = s < m && p < p_end;
-      xs[q][s] = ok ? (double)X[(long)s * N + p] : 0.0;
-      if (!same) ys[q][s] = ok ? (double)Y[(long)s * N + p] : 0.0;
+      const bool ok = e < mp * GSLAB && st < m && p < p_end;
+      px[r] = ok ? X[(long)st * N + p] : F(0);
+      if (!SYM) py[r] = ok ? Y[(long)st * N + p] : F(0);
     }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 256 * r;
+      if (e < mp * GSLAB) {
+        const int st = e / GSLAB, q = e - st * GSLAB;
+        xs[q][st] = (double)px[r];
+        if (!SYM) ys[q][st] = (double)py[r];
+      }
+    }
+  };
+  load(p_begin);
+  for (long p0 = p_begin; p0 < p_end; p0 += GSLAB) {
+    stage();
     __syncthreads();
-    const double(*yy)[MAXM + 2] = same ? xs : ys;
+    if (p0 + GSLAB < p_end) load(p0 + GSLAB);   // in flight during the MFMAs below
 #pragma unroll
     for (int k0 = 0; k0 < GSLAB; k0 += 4) {
       const int kq = k0 + (lane >> 4);
 #pragma unroll
-      for (int t = 0; t < GMAXT; ++t) {
-        const int tile = wave + 4 * t;
-        if (tile < nt * nt) {
-          const int ti = tile / nt, tj = tile - ti * nt;
-          const double a = xs[kq][ti * 16 + (lane & 15)];
-          const double b = yy[kq][tj * 16 + (lane & 15)];
+      for (int t = 0; t < TPW; ++t) {
+        if (TPW * 4 == NTILE || wave + 4 * t < NTILE) {
+          const double a = xs[kq][tiv[t] * 16 + (lane & 15)];
+          const double b = SYM ? xs[kq][tjv[t] * 16 + (lane & 15)] : ys[kq][tjv[t] * 16 + (lane & 15)];
           acc[t] = mfma16(a, b, acc[t]);
         }
       }
@@ -84,14 +131,13 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
   }
   double* out = g.partials + ((long)prod * gridDim.x + blockIdx.x) * (long)mp * mp;
 #pragma unroll
-  for (int t = 0; t < GMAXT; ++t) {
-    const int tile = wave + 4 * t;
-    if (tile < nt * nt) {
-      const int ti = tile / nt, tj = tile - ti * nt;
+  for (int t = 0; t < TPW; ++t) {
+    if (wave + 4 * t < NTILE) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = ti * 16 + drow(lane, r), j = tj * 16 + (lane & 15);
+        const int i = tiv[t] * 16 + drow(lane, r), j = tjv[t] * 16 + (lane & 15);
         out[(long)i * mp + j] = acc[t][r];
+        if (SYM && tiv[t] != tjv[t]) out[(long)j * mp + i] = acc[t][r];
       }
     }
   }
@@ -129,6 +175,54 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return r;
 }
 
+// phase stamps from the 100 MHz constant clock (diagnostics only)
+__device__ __forceinline__ void stamp(const SmallDenseArgs& d, int i) {
+  if (d.ticks && threadIdx.x == 0) d.ticks[i] = (long long)__builtin_amdgcn_s_memrealtime();
+}
+
+// Triangular solves on the LDS matrix sh (row stride LD) with the Cholesky
+// factor L (global, row stride mp, lower).  Right-looking: one barrier per
+// pivot, all right-hand sides in parallel; rows are scaled by 1/L_ii at the end.
+//   ROWS = true : sh <- L^-1 sh      (forward, columns are right-hand sides)
+//   ROWS = false: sh <- sh L^-T      (forward, rows are right-hand sides)
+template <bool ROWS>
+__device__ void lower_solve(double* sh, int LD, const double* __restrict__ L, int mp, int m) {
+  for (int k = 0; k < m; ++k) {
+    const double inv = 1.0 / L[(long)k * mp + k];
+    const int rem = m - k - 1;
+    for (int e = threadIdx.x; e < rem * m; e += SD_THREADS) {
+      const int i = k + 1 + e / m, j = e % m;
+      const double lik = L[(long)i * mp + k];
+      if (ROWS) sh[i * LD + j] -= lik * (sh[k * LD + j] * inv);
+      else sh[j * LD + i] -= lik * (sh[j * LD + k] * inv);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < m * m; e += SD_THREADS) {
+    const int i = e / m, j = e % m;
+    if (ROWS) sh[i * LD + j] /= L[(long)i * mp + i];
+    else sh[j * LD + i] /= L[(long)i * mp + i];
+  }
+  __syncthreads();
+}
+
+// sh <- L^-T sh (backward, columns are right-hand sides)
+__device__ void upper_solve_rows(double* sh, int LD, const double* __restrict__ L, int mp, int m) {
+  for (int k = m - 1; k >= 0; --k) {
+    const double inv = 1.0 / L[(long)k * mp + k];
+    for (int e = threadIdx.x; e < k * m; e += SD_THREADS) {
+      const int i = e / m, j = e % m;
+      sh[i * LD + j] -= L[(long)k * mp + i] * (sh[k * LD + j] * inv);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < m * m; e += SD_THREADS) {
+    const int i = e / m, j = e % m;
+    sh[i * LD + j] /= L[(long)i * mp + i];
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs d) {
   extern __shared__ double sh[];  // mp x LD
   __shared__ double red[20];
@@ -142,6 +236,7 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   auto A = [&](int i, int j) -> double& { return sh[i * LD + j]; };
 
   if (tid == 0) flag = -1;
+  stamp(d, 0);
   __syncthreads();
   // ---- Cholesky of S in LDS (right-looking)
   for (int e = tid; e < m * m; e += SD_THREADS) A(e / m, e % m) = d.S[(e / m) * (long)d.mp + e % m];
@@ -182,18 +277,12 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   __threadfence_block();
   __syncthreads();
 
+  stamp(d, 1);
   if (d.mode == SD_ORTHO) {
-    // C = L^-T: back substitution on the identity, one column per thread
+    // C = L^-T: backward solve on the identity
     for (int e = tid; e < m * m; e += SD_THREADS) A(e / m, e % m) = (e / m == e % m) ? 1.0 : 0.0;
     __syncthreads();
-    for (int j = tid; j < m; j += SD_THREADS) {
-      for (int i = m - 1; i >= 0; --i) {
-        double s = A(i, j);
-        for (int k = i + 1; k < m; ++k) s -= L[(long)k * d.mp + i] * A(k, j);
-        A(i, j) = s / L[(long)i * d.mp + i];
-      }
-    }
-    __syncthreads();
+    upper_solve_rows(sh, LD, L, d.mp, m);
     for (int e = tid; e < d.mp * d.mp; e += SD_THREADS) {
       const int i = e / d.mp, j = e % d.mp;
       d.C[e] = (i < m && j < m) ? A(i, j) : 0.0;
@@ -214,22 +303,8 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
     }
   }
   __syncthreads();
-  for (int j = tid; j < m; j += SD_THREADS) {
-    for (int i = 0; i < m; ++i) {
-      double s = A(i, j);
-      for (int k = 0; k < i; ++k) s -= L[(long)i * d.mp + k] * A(k, j);
-      A(i, j) = s / L[(long)i * d.mp + i];
-    }
-  }
-  __syncthreads();
-  for (int j = tid; j < m; j += SD_THREADS) {
-    for (int i = 0; i < m; ++i) {
-      double s = A(j, i);
-      for (int k = 0; k < i; ++k) s -= L[(long)i * d.mp + k] * A(j, k);
-      A(j, i) = s / L[(long)i * d.mp + i];
-    }
-  }
-  __syncthreads();
+  lower_solve<true>(sh, LD, L, d.mp, m);    // X = L^-1 Hs
+  lower_solve<false>(sh, LD, L, d.mp, m);   // A = X L^-T
   for (int e = tid; e < m * m; e += SD_THREADS) {
     const int i = e / m, j = e % m;
     if (i < j) {
@@ -240,6 +315,7 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   }
   __syncthreads();
 
+  stamp(d, 2);
   // ---- cyclic Jacobi, round-robin ordering over n = m rounded up to even.
   // One step rotates n/2 disjoint pairs at once.  A' = J^T A J is applied as
   // independent 2x2 blocks: block (k, l) = rows {p_k, q_k} x columns {p_l, q_l}
@@ -261,7 +337,10 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   for (int i = tid; i < m; i += SD_THREADS) dmax = fmax(dmax, fabs(A(i, i)));
   const double floor_abs = 32.0 * 2.220446049250313e-16 * fmax(block_max(dmax, red), 1e-300) / d.tol;
   const double rot_tol = 0.125 * d.tol;
-  long nrot = 0;
+  // eigenvectors accumulate in U (global, L2 resident): U <- U J each step
+  double* U = d.rot;
+  for (int e = tid; e < m * m; e += SD_THREADS) U[(e / m) * (long)d.mp + e % m] = (e / m == e % m) ? 1.0 : 0.0;
+  __syncthreads();
   int sweep = 0;
   bool converged = false;
   int gstep = 0;
@@ -311,12 +390,17 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
       }
       __syncthreads();
       if (step_active[cur]) {   // uniform
-        for (int k = tid; k < half; k += SD_THREADS) {
-          double* slot = d.rot + (nrot + k) * 4;
-          slot[0] = cs[k][0];
-          slot[1] = cs[k][1];
-          slot[2] = (double)pq[k][0];
-          slot[3] = (double)pq[k][1];
+        // columns p, q of U (rows in parallel; a row's pairs are neighbouring threads)
+        for (int e = tid; e < half * m; e += SD_THREADS) {
+          const int r = e / half, k = e - r * half;
+          const int pk = pq[k][0], qk = pq[k][1];
+          if (qk < m) {
+            const double ck = cs[k][0], sk = cs[k][1];
+            double* ur = U + (long)r * d.mp;
+            const double up = ur[pk], uq = ur[qk];
+            ur[pk] = ck * up - sk * uq;
+            ur[qk] = sk * up + ck * uq;
+          }
         }
         for (int e = tid; e < half * half; e += SD_THREADS) {
           const int k = e / half, l = e - k * half;
@@ -332,11 +416,11 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
           A(qk, pl) = cl * r10 - sl * r11;
           A(qk, ql) = sl * r10 + cl * r11;
         }
-        nrot += half;
       }
       __syncthreads();
     }
   }
+  stamp(d, 3);
   if (!converged) {
     if (tid == 0) d.status[0] = ST_EIG_NO_CONV, d.status[1] = sweep;
     return;
@@ -359,32 +443,12 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   }
   __threadfence_block();
   __syncthreads();
-  // U = product of the logged rotations, rebuilt in LDS
-  for (int e = tid; e < m * m; e += SD_THREADS) A(e / m, e % m) = (e / m == e % m) ? 1.0 : 0.0;
+  // U into LDS (A is no longer needed)
+  for (int e = tid; e < m * m; e += SD_THREADS) A(e / m, e % m) = U[(e / m) * (long)d.mp + e % m];
   __syncthreads();
-  for (long base = 0; base < nrot; base += half) {
-    for (int e = tid; e < half * m; e += SD_THREADS) {
-      const int k = e / m, r = e % m;
-      const double* rr = d.rot + (base + k) * 4;
-      const int p = (int)rr[2], q = (int)rr[3];
-      if (q < m) {
-        const double c = rr[0], s = rr[1];
-        const double ap = A(r, p), aq = A(r, q);
-        A(r, p) = c * ap - s * aq;
-        A(r, q) = s * ap + c * aq;
-      }
-    }
-    __syncthreads();
-  }
-  // C = L^-T U (column per thread, in place, bottom up)
-  for (int j = tid; j < m; j += SD_THREADS) {
-    for (int i = m - 1; i >= 0; --i) {
-      double s = A(i, j);
-      for (int k = i + 1; k < m; ++k) s -= L[(long)k * d.mp + i] * A(k, j);
-      A(i, j) = s / L[(long)i * d.mp + i];
-    }
-  }
-  __syncthreads();
+  stamp(d, 4);
+  // C = L^-T U
+  upper_solve_rows(sh, LD, L, d.mp, m);
   for (int e = tid; e < d.mp * d.mp; e += SD_THREADS) d.C[e] = 0.0;
   __syncthreads();
   for (int e = tid; e < m * m; e += SD_THREADS) {
@@ -392,24 +456,55 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
     d.C[(long)i * d.mp + rank[j]] = A(i, j);
   }
   if (tid == 0) d.status[0] = ST_OK, d.status[1] = sweep;
+  stamp(d, 5);
 }
 
 // ------------------------------------------------------------------ rotation + residual epilogue
 // Work-group: 256 threads = 4 waves; each wave owns strips of 16 points and all
 // mp/16 output tiles of states.  Psi[j][p] = sum_i C[i][j] Phi[i][p].
-constexpr int RMAXT = MAXM / 16;
+// MT is the MFMA operand type: double (v_mfma_f64_16x16x4f64, float64 plans)
+// or float (v_mfma_f32_16x16x4f32, float32 plans: C rounded to float32, the
+// rotation of float32 states then loses nothing beyond float32 storage).
+// A strip's B operands are loaded in one go before its MFMA chain.
 
-template <typename F, bool WITH_H>
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename MT>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  using acc = d4;
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) { return mfma16(a, b, c); }
+  static __device__ __forceinline__ int row(int lane, int r) { return drow(lane, r); }
+};
+// float32 16x16x4 layout (measured): D[4 * (l / 16) + r][l % 16]
+template <>
+struct Mfma<float> {
+  using acc = f4;
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename F, typename MT, bool WITH_H, int NT>
 __global__ __launch_bounds__(256) void rotate_kernel(RotateArgs r) {
-  __shared__ double cT[MAXM * MAXM];  // cT[j * mp + i] = C[i][j]
+  __shared__ MT cT[MAXM * MAXM];      // cT[j * mp + i] = C[i][j]
+  __shared__ double thl[MAXM];
+  __shared__ double rs[4][MAXM];
   if (r.status && r.status[0] != ST_OK) return;   // uniform: leave the states untouched
-  const int m = r.m, mp = r.mp, nt = mp / 16;
+  using M = Mfma<MT>;
+  using acc_t = typename M::acc;
+  // NT = mp / 16 output tiles at compile time: no predicated MFMAs
+  constexpr int mp = NT * 16, nk = NT * 4;
+  const int m = r.m;
   const long N = r.N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int e = tid; e < mp * mp; e += 256) {
     const int i = e / mp, j = e - i * mp;
-    cT[j * mp + i] = r.C[e];
+    cT[j * mp + i] = (MT)r.C[e];
   }
+  for (int j = tid; j < mp; j += 256) thl[j] = (WITH_H && j < m) ? r.theta[j] : 0.0;
   __syncthreads();
   // Psi may alias Phi (in-place rotation): every output point depends only on
   // the same point of the inputs, and each 16-point strip is read completely
@@ -419,58 +514,69 @@ __global__ __launch_bounds__(256) void rotate_kernel(RotateArgs r) {
   F* Psi = reinterpret_cast<F*>(r.Psi);
   F* HPsi = reinterpret_cast<F*>(r.HPsi);
 
-  double res[RMAXT][4];
+  float res[NT][4];   // residual partial sums (a convergence measure: float32 suffices)
 #pragma unroll
-  for (int t = 0; t < RMAXT; ++t)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) res[t][q] = 0.0;
-  double th[RMAXT][4];
-#pragma unroll
-  for (int t = 0; t < RMAXT; ++t)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = t * 16 + drow(lane, q);
-      th[t][q] = (WITH_H && j < m) ? r.theta[j] : 0.0;
-    }
+    for (int q = 0; q < 4; ++q) res[t][q] = 0.f;
 
   const long p_begin = (long)blockIdx.x * r.chunk;
   const long p_end = min(N, p_begin + r.chunk);
   for (long p0 = p_begin + 16 * wave; p0 < p_end; p0 += 64) {
     const long p = p0 + (lane & 15);
     const bool pok = p < p_end;
-    d4 ap[RMAXT], ah[RMAXT];
+    // B operands in groups of KG k-steps; the next group's loads are issued
+    // before the current group's MFMAs so their latency hides behind them.
+    constexpr int KG = 4;
+    MT b[KG], bh[KG], nb[KG], nbh[KG];
+    auto load_group = [&](int k0, MT (&x)[KG], MT (&xh)[KG]) {
 #pragma unroll
-    for (int t = 0; t < RMAXT; ++t) ap[t] = ah[t] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int i0 = 0; i0 < mp; i0 += 4) {
-      const int i = i0 + (lane >> 4);
-      const bool ok = pok && i < m;
-      const double b = ok ? (double)Phi[(long)i * N + p] : 0.0;
-      const double bh = (WITH_H && ok) ? (double)HPhi[(long)i * N + p] : 0.0;
+      for (int kk = 0; kk < KG; ++kk) {
+        const int k = k0 + kk;
+        const int i = 4 * k + (lane >> 4);
+        const bool ok = k < nk && pok && i < m;
+        x[kk] = ok ? (MT)Phi[(long)i * N + p] : MT(0);
+        xh[kk] = (WITH_H && ok) ? (MT)HPhi[(long)i * N + p] : MT(0);
+      }
+    };
+    load_group(0, b, bh);
+    acc_t ap[NT], ah[NT];
 #pragma unroll
-      for (int t = 0; t < RMAXT; ++t) {
-        if (t < nt) {
-          // A (16x4) = C^T tile: A[jj][kk] = C[i0 + kk][t*16 + jj]
-          const double a = cT[(t * 16 + (lane & 15)) * mp + i0 + (lane >> 4)];
-          ap[t] = mfma16(a, b, ap[t]);
-          if (WITH_H) ah[t] = mfma16(a, bh, ah[t]);
+    for (int t = 0; t < NT; ++t) ap[t] = ah[t] = acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < nk; k0 += KG) {
+      if (k0 + KG < nk) load_group(k0 + KG, nb, nbh);
+#pragma unroll
+      for (int kk = 0; kk < KG; ++kk) {
+        const int k = k0 + kk;
+        if (KG <= nk || k < nk) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            // A (16x4) = C^T tile: A[jj][kk] = C[4k + kk][t*16 + jj]
+            const MT a = cT[(t * 16 + (lane & 15)) * mp + 4 * k + (lane >> 4)];
+            ap[t] = M::mma(a, b[kk], ap[t]);
+            if (WITH_H) ah[t] = M::mma(a, bh[kk], ah[t]);
+          }
         }
+      }
+#pragma unroll
+      for (int kk = 0; kk < KG; ++kk) {
+        b[kk] = nb[kk];
+        bh[kk] = nbh[kk];
       }
     }
 #pragma unroll
-    for (int t = 0; t < RMAXT; ++t) {
-      if (t < nt) {
+    for (int t = 0; t < NT; ++t) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int j = t * 16 + drow(lane, q);
-          if (j < m && pok) {
-            const F ps = (F)ap[t][q];
-            Psi[(long)j * N + p] = ps;
-            if (WITH_H) {
-              const F hs = (F)ah[t][q];
-              if (HPsi) HPsi[(long)j * N + p] = hs;
-              const double dv = (double)hs - th[t][q] * (double)ps;
-              res[t][q] += dv * dv;
-            }
+      for (int q = 0; q < 4; ++q) {
+        const int j = t * 16 + M::row(lane, q);
+        if (j < m && pok) {
+          const F ps = (F)ap[t][q];
+          Psi[(long)j * N + p] = ps;
+          if (WITH_H) {
+            const F hs = (F)ah[t][q];
+            if (HPsi) HPsi[(long)j * N + p] = hs;
+            const double dv = (double)hs - thl[j] * (double)ps;
+            res[t][q] += (float)(dv * dv);
           }
         }
       }
@@ -478,15 +584,14 @@ __global__ __launch_bounds__(256) void rotate_kernel(RotateArgs r) {
   }
   if (!WITH_H) return;
   // reduce residual partials over the 16 lanes sharing a state, then over waves
-  __shared__ double rs[4][MAXM];
 #pragma unroll
-  for (int t = 0; t < RMAXT; ++t)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       double v = res[t][q];
       for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
-      const int j = t * 16 + drow(lane, q);
-      if ((lane & 15) == 0 && t < nt) rs[wave][j] = v;
+      const int j = t * 16 + M::row(lane, q);
+      if ((lane & 15) == 0) rs[wave][j] = v;
     }
   __syncthreads();
   for (int j = tid; j < mp; j += 256) {
@@ -518,13 +623,38 @@ __global__ void variance_kernel(const double* S, const double* M, int m, int mp,
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_gram(int is_double, const GramArgs& g, int nprod, int nchunks, hipStream_t st) {
-  dim3 grid(nchunks, nprod);
-  if (is_double)
-    hipLaunchKernelGGL(gram_partial_kernel<double>, grid, dim3(256), 0, st, g);
-  else
-    hipLaunchKernelGGL(gram_partial_kernel<float>, grid, dim3(256), 0, st, g);
+template <typename F, bool SYM>
+static hipError_t launch_gram_t(const GramArgs& g, int nprod, int nchunks, hipStream_t st) {
+  dim3 grid(nchunks, nprod), block(256);
+  switch (g.mp / 16) {
+    case 1: hipLaunchKernelGGL((gram_partial_kernel<F, 1, SYM>), grid, block, 0, st, g); break;
+    case 2: hipLaunchKernelGGL((gram_partial_kernel<F, 2, SYM>), grid, block, 0, st, g); break;
+    case 3: hipLaunchKernelGGL((gram_partial_kernel<F, 3, SYM>), grid, block, 0, st, g); break;
+    case 4: hipLaunchKernelGGL((gram_partial_kernel<F, 4, SYM>), grid, block, 0, st, g); break;
+    case 5: hipLaunchKernelGGL((gram_partial_kernel<F, 5, SYM>), grid, block, 0, st, g); break;
+    case 6: hipLaunchKernelGGL((gram_partial_kernel<F, 6, SYM>), grid, block, 0, st, g); break;
+    case 7: hipLaunchKernelGGL((gram_partial_kernel<F, 7, SYM>), grid, block, 0, st, g); break;
+    case 8: hipLaunchKernelGGL((gram_partial_kernel<F, 8, SYM>), grid, block, 0, st, g); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+
+// Products with X == Y (overlaps of one block with itself) run as symmetric
+// launches; the others as general ones.  Partials land in g.partials[prod].
+hipError_t launch_gram(int is_double, const GramArgs& g, int nprod, int nchunks, hipStream_t st) {
+  for (int i = 0; i < nprod; ++i) {
+    GramArgs one = g;
+    one.X[0] = g.X[i];
+    one.Y[0] = g.Y[i];
+    one.partials = g.partials + (long)i * nchunks * g.mp * g.mp;
+    const bool sym = g.X[i] == g.Y[i];
+    hipError_t e;
+    if (is_double) e = sym ? launch_gram_t<double, true>(one, 1, nchunks, st) : launch_gram_t<double, false>(one, 1, nchunks, st);
+    else e = sym ? launch_gram_t<float, true>(one, 1, nchunks, st) : launch_gram_t<float, false>(one, 1, nchunks, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_reduce(const double* in, int nparts, long count, int ncomp, double* out, hipStream_t st) {
@@ -544,16 +674,29 @@ hipError_t launch_small_dense(const SmallDenseArgs& d, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_rotate(int is_double, bool with_h, const RotateArgs& r, int nchunks, hipStream_t st) {
-  dim3 grid(nchunks);
-  if (is_double) {
-    if (with_h) hipLaunchKernelGGL((rotate_kernel<double, true>), grid, dim3(256), 0, st, r);
-    else hipLaunchKernelGGL((rotate_kernel<double, false>), grid, dim3(256), 0, st, r);
-  } else {
-    if (with_h) hipLaunchKernelGGL((rotate_kernel<float, true>), grid, dim3(256), 0, st, r);
-    else hipLaunchKernelGGL((rotate_kernel<float, false>), grid, dim3(256), 0, st, r);
+template <typename F, typename MT, bool H>
+static hipError_t launch_rotate_t(const RotateArgs& r, int nchunks, hipStream_t st) {
+  dim3 grid(nchunks), block(256);
+  switch (r.mp / 16) {
+    case 1: hipLaunchKernelGGL((rotate_kernel<F, MT, H, 1>), grid, block, 0, st, r); break;
+    case 2: hipLaunchKernelGGL((rotate_kernel<F, MT, H, 2>), grid, block, 0, st, r); break;
+    case 3: hipLaunchKernelGGL((rotate_kernel<F, MT, H, 3>), grid, block, 0, st, r); break;
+    case 4: hipLaunchKernelGGL((rotate_kernel<F, MT, H, 4>), grid, block, 0, st, r); break;
+    case 5: hipLaunchKernelGGL((rotate_kernel<F, MT, H, 5>), grid, block, 0, st, r); break;
+    case 6: hipLaunchKernelGGL((rotate_kernel<F, MT, H, 6>), grid, block, 0, st, r); break;
+    case 7: hipLaunchKernelGGL((rotate_kernel<F, MT, H, 7>), grid, block, 0, st, r); break;
+    case 8: hipLaunchKernelGGL((rotate_kernel<F, MT, H, 8>), grid, block, 0, st, r); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_rotate(int is_double, bool with_h, const RotateArgs& r, int nchunks, hipStream_t st) {
+  if (is_double)
+    return with_h ? launch_rotate_t<double, double, true>(r, nchunks, st)
+                  : launch_rotate_t<double, double, false>(r, nchunks, st);
+  return with_h ? launch_rotate_t<float, float, true>(r, nchunks, st)
+                : launch_rotate_t<float, float, false>(r, nchunks, st);
 }
 
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st) {

@@ -23,11 +23,12 @@ struct SmallDenseArgs {
   const double* S;      // mp x mp overlap
   const double* Hs;     // mp x mp projected H (SD_RR)
   double* L;            // mp x mp workspace (Cholesky factor)
-  double* rot;          // rotation log, 4 doubles per rotation
+  double* rot;          // mp x mp workspace: the Jacobi eigenvectors U
   double* scratch;      // >= 2*MAXM doubles
   double* C;            // out: mp x mp, Psi_j = sum_i C[i][j] Phi_i
   double* theta;        // out: m Ritz values ascending (SD_RR)
   int* status;          // out: [code, detail]
+  long long* ticks;     // optional out: constant-clock stamps at phase ends (8 entries)
   int m, mp, mode, max_sweeps;
   double tol;           // Jacobi: converged when |a_ij| <= tol * max(sqrt|a_ii a_jj|, floor)
   double pivot_tol;     // Cholesky: pivot must exceed pivot_tol * original diagonal

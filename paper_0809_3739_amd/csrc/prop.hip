@@ -44,9 +44,20 @@ struct PlaneShape {
 // Waves per SIMD that the LDS footprint admits (2 work-groups per CU for a
 // float32 128^2 plane): the register budget is capped to match, so that one
 // work-group's loads overlap another's LDS work.
+// LDS row stride (complex elements) of the plane: the row phase maps TX lanes to
+// each of 32/TX rows of a half-wave, so rows are offset by TX (mod 32) complex
+// slots to land in distinct LDS banks.
+template <int NX>
+constexpr int plane_srow() {
+  constexpr int nxh = NX / 2 + 1, tx = Plan<NX / 2>::T;
+  int s = nxh;
+  while (!((s % 32) % tx == 0 && ((s % 32) / tx) % 2 == 1)) ++s;
+  return s;
+}
+
 template <typename F, int NX>
 struct PlaneOcc {
-  static constexpr int LDS = NX * (NX / 2 + 1) * 2 * (int)sizeof(F);
+  static constexpr int LDS = NX * plane_srow<NX>() * 2 * (int)sizeof(F);
   static constexpr int WG = (160 * 1024 / LDS) < 1 ? 1 : (160 * 1024 / LDS);
   static constexpr int W = WG * (PlaneShape<NX>::BLOCK / 64) / 4;
   static constexpr int value = W < 1 ? 1 : (W > 8 ? 8 : W);
@@ -70,25 +81,60 @@ void plane_kernel(PlaneArgs a) {
   constexpr int NCF = LX;                          // column FFTs
   constexpr int RPR = BLOCK / TX;                  // rows per round
   constexpr int XR = (NY + RPR - 1) / RPR;         // row rounds
-  constexpr int SROW = NXH;                        // LDS row stride (complex)
+  constexpr int SROW = plane_srow<NX>();           // LDS row stride (complex), bank-spread
   static_assert(BLOCK % TX == 0, "block must hold whole row transforms");
+  // a row's TX lanes are consecutive lanes of one wavefront (tx = tid % TX)
+  constexpr bool ROWWAVE = (64 % TX == 0);
   static_assert(NCF * TY <= BLOCK, "one column round");
   static_assert(NCF % 2 == 0, "column pairs");
 
   __shared__ cx<F> lds[NY * SROW];
+  // twiddle tables staged in LDS (they sit on the FFT critical path)
+  __shared__ cx<F> tw_x[LX], tw_y[NY], tw_w[HALF + 1];
 
   const int tid = threadIdx.x;
   const int z = blockIdx.x;
   const long s = (long)blockIdx.y + a.state0;
   const long plane_real = (long)NY * NX;
   const long plane_spec = (long)NY * NXH;
-  const long real_off = s * a.real_state_stride + (long)z * plane_real;
-  const long spec_off = s * a.spec_state_stride + (long)z * plane_spec;
-  const long fac_off = (long)z * plane_real;
+  const long z_real = (long)z * plane_real;
+  const long z_spec = (long)z * plane_spec;
+  // this state's arrays (plane z offsets added below)
+  const F* rin;
+  F* rout;
+  cx<F>* spec;
+  long chain_stride;
+  const F* facb;
+  if (a.desc) {
+    const StateDesc& d = a.desc[s];
+    rin = reinterpret_cast<const F*>(d.real_in);
+    rout = reinterpret_cast<F*>(d.real_out);
+    chain_stride = d.chain_stride;
+    spec = reinterpret_cast<cx<F>*>(d.spec) + (long)a.chain * chain_stride;
+    facb = reinterpret_cast<const F*>(MODE == PM_HTAIL ? d.V : d.fac);
+  } else {
+    rin = reinterpret_cast<const F*>(a.real_in) + s * a.real_state_stride;
+    rout = reinterpret_cast<F*>(a.real_out) + s * a.real_state_stride;
+    spec = reinterpret_cast<cx<F>*>(a.spec) + s * a.spec_state_stride;
+    chain_stride = a.chain_stride;
+    facb = reinterpret_cast<const F*>(a.fac);
+  }
+  const F* facz = (MODE == PM_HTAIL || MODE == PM_TAIL || a.fac_index < 0 || !facb)
+                      ? facb
+                      : facb + (long)a.fac_index * a.fac_table_stride;
 
-  const cx<F>* rx = reinterpret_cast<const cx<F>*>(a.rx);
-  const cx<F>* ry = reinterpret_cast<const cx<F>*>(a.ry);
-  const cx<F>* wpost = reinterpret_cast<const cx<F>*>(a.wpost);   // W^k, k = 0..NX/4
+  {
+    const cx<F>* gx = reinterpret_cast<const cx<F>*>(a.rx);
+    const cx<F>* gy = reinterpret_cast<const cx<F>*>(a.ry);
+    const cx<F>* gw = reinterpret_cast<const cx<F>*>(a.wpost);
+    for (int i = tid; i < LX; i += BLOCK) tw_x[i] = gx[i];
+    for (int i = tid; i < NY; i += BLOCK) tw_y[i] = gy[i];
+    for (int i = tid; i <= HALF; i += BLOCK) tw_w[i] = gw[i];
+  }
+  const cx<F>* rx = tw_x;
+  const cx<F>* ry = tw_y;
+  const cx<F>* wpost = tw_w;   // W^k, k = 0..NX/4
+  __syncthreads();
 
   // row phase mapping
   const int tx = tid % TX, rloc = tid / TX;
@@ -198,8 +244,8 @@ void plane_kernel(PlaneArgs a) {
   };
 
   if constexpr (MODE == PM_FWD) {
-    const F* __restrict__ src = reinterpret_cast<const F*>(a.real_in) + real_off;
-    const F* __restrict__ fac = a.fac ? reinterpret_cast<const F*>(a.fac) + fac_off : nullptr;
+    const F* __restrict__ src = rin + z_real;
+    const F* __restrict__ fac = (a.fac_index >= 0 && facz) ? facz + z_real : nullptr;
 #pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
@@ -220,16 +266,16 @@ void plane_kernel(PlaneArgs a) {
           }
         }
       }
-      fft<LX, -1>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
+      fft<LX, -1, ROWWAVE>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
       if (act) {
 #pragma unroll
         for (int m = 0; m < EX; ++m) lds[row * SROW + tx + TX * m] = v[m];
       }
     }
-    column_forward_store(reinterpret_cast<cx<F>*>(a.spec_out) + spec_off);
+    column_forward_store(spec + z_spec);
   } else if constexpr (MODE == PM_LINK) {
-    column_inverse(reinterpret_cast<const cx<F>*>(a.spec_in) + spec_off);
-    const F* __restrict__ fac = reinterpret_cast<const F*>(a.fac) + fac_off;
+    column_inverse(spec + z_spec);
+    const F* __restrict__ fac = facz + z_real;
 #pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
@@ -245,19 +291,19 @@ void plane_kernel(PlaneArgs a) {
           fv[m] = f2[tx + TX * m];
         }
       }
-      fft<LX, +1>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
+      fft<LX, +1, ROWWAVE>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
 #pragma unroll
       for (int m = 0; m < EX; ++m) {
         v[m].x *= fv[m].x;
         v[m].y *= fv[m].y;
       }
-      fft<LX, -1>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
+      fft<LX, -1, ROWWAVE>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
       if (act) {
 #pragma unroll
         for (int m = 0; m < EX; ++m) lds[row * SROW + tx + TX * m] = v[m];
       }
     }
-    column_forward_store(reinterpret_cast<cx<F>*>(a.spec_out) + spec_off);
+    column_forward_store(spec + z_spec);
   } else if constexpr (MODE == PM_TAIL) {
     double acc[XR][EX][2];
 #pragma unroll
@@ -266,17 +312,17 @@ void plane_kernel(PlaneArgs a) {
       for (int m = 0; m < EX; ++m) acc[rr][m][0] = acc[rr][m][1] = 0.0;
     // the next chain's column loads are issued before this chain's row work,
     // so their latency hides behind it (one work-group per CU here)
-    const cx<F>* spec0 = reinterpret_cast<const cx<F>*>(a.spec_in) + spec_off;
+    const cx<F>* spec0 = spec + z_spec;
     cx<F> vc[EY];
     column_load(spec0, vc);
     for (int k = 0; k < a.K; ++k) {
-      const F* __restrict__ fac = reinterpret_cast<const F*>(a.fac) + (long)(2 * k + 1) * a.fac_table_stride + fac_off;
+      const F* __restrict__ fac = facb + (long)(2 * k + 1) * a.fac_table_stride + z_real;
       const double ck = a.coef[k];
       column_inverse_regs(vc);
       // (float64 planes have no registers to spare for the prefetch)
       if (k + 1 < a.K) {
         if constexpr (sizeof(F) == 4) {
-          column_load(spec0 + (long)(k + 1) * a.chain_stride, vc);
+          column_load(spec0 + (long)(k + 1) * chain_stride, vc);
         }
       }
 #pragma unroll
@@ -289,7 +335,7 @@ void plane_kernel(PlaneArgs a) {
 #pragma unroll
           for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + tx + TX * m];
         }
-        fft<LX, +1>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
+        fft<LX, +1, ROWWAVE>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
         if (act) {
           const cx<F>* f2 = reinterpret_cast<const cx<F>*>(fac + (long)row * NX);
 #pragma unroll
@@ -302,10 +348,10 @@ void plane_kernel(PlaneArgs a) {
       }
       __syncthreads();
       if constexpr (sizeof(F) != 4) {
-        if (k + 1 < a.K) column_load(spec0 + (long)(k + 1) * a.chain_stride, vc);
+        if (k + 1 < a.K) column_load(spec0 + (long)(k + 1) * chain_stride, vc);
       }
     }
-    F* __restrict__ dst = reinterpret_cast<F*>(a.real_out) + real_off;
+    F* __restrict__ dst = rout + z_real;
 #pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
@@ -316,10 +362,10 @@ void plane_kernel(PlaneArgs a) {
       }
     }
   } else {  // PM_HTAIL
-    column_inverse(reinterpret_cast<const cx<F>*>(a.spec_in) + spec_off);
-    const F* __restrict__ phi = reinterpret_cast<const F*>(a.real_in) + real_off;
-    const F* __restrict__ V = reinterpret_cast<const F*>(a.fac) + fac_off;
-    F* __restrict__ dst = reinterpret_cast<F*>(a.real_out) + real_off;
+    column_inverse(spec + z_spec);
+    const F* __restrict__ phi = rin + z_real;
+    const F* __restrict__ V = facb + z_real;
+    F* __restrict__ dst = rout + z_real;
 #pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
@@ -330,7 +376,7 @@ void plane_kernel(PlaneArgs a) {
 #pragma unroll
         for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + tx + TX * m];
       }
-      fft<LX, +1>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
+      fft<LX, +1, ROWWAVE>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
       if (act) {
         const cx<F>* p2 = reinterpret_cast<const cx<F>*>(phi + (long)row * NX);
         const cx<F>* v2 = reinterpret_cast<const cx<F>*>(V + (long)row * NX);
@@ -356,7 +402,11 @@ __global__ __launch_bounds__(256) void pencil_kernel(PencilArgs a) {
   using P = Plan<NZ>;
   constexpr int T = P::T, E = P::E;
   constexpr int C = PencilCols<NZ>::value;
-  __shared__ cx<F> lds[T > 1 ? NZ * C : 1];
+  constexpr int CP = C + 1;   // padded row: the T lanes of a column hit different banks
+  __shared__ cx<F> lds[T > 1 ? NZ * CP : 1];
+
+  __shared__ cx<F> rz_s[NZ];
+  __shared__ F tz_s[NZ];
 
   const int tid = threadIdx.x;
   const int col = tid % C, t = tid / C;
@@ -364,18 +414,34 @@ __global__ __launch_bounds__(256) void pencil_kernel(PencilArgs a) {
   const int gcol = blockIdx.x * C + col;
   const bool act = gcol < a.M;
   const int gc = act ? gcol : 0;
-  cx<F>* data = reinterpret_cast<cx<F>*>(a.data) + s * a.state_stride;
-  const cx<F>* rz = reinterpret_cast<const cx<F>*>(a.rz);
-  const F* tx = reinterpret_cast<const F*>(a.tx);
-  const F* ty = reinterpret_cast<const F*>(a.ty);
-  const F* tz = reinterpret_cast<const F*>(a.tz);
+  cx<F>* data;
+  const F* tab;
+  if (a.desc) {
+    const StateDesc& d = a.desc[s];
+    data = reinterpret_cast<cx<F>*>(d.spec) + (long)a.chain * d.chain_stride;
+    tab = a.desc_tables == 0
+              ? reinterpret_cast<const F*>(d.kin) + (long)a.chain * (a.NXH + a.NY + NZ)
+              : reinterpret_cast<const F*>(d.hk);
+  } else {
+    data = reinterpret_cast<cx<F>*>(a.data) + s * a.state_stride;
+    tab = reinterpret_cast<const F*>(a.tab);
+  }
+  const F* tx = tab;
+  const F* ty = tab + a.NXH;
+  for (int i = tid; i < NZ; i += 256) {
+    rz_s[i] = reinterpret_cast<const cx<F>*>(a.rz)[i];
+    tz_s[i] = tab[a.NXH + a.NY + i];
+  }
+  const cx<F>* rz = rz_s;
+  const F* tz = tz_s;
 
   cx<F> v[E];
   if (act) {
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = data[(long)(t + T * m) * a.M + gcol];
   }
-  auto buf = [&](int i) { return &lds[i * C + col]; };
+  __syncthreads();   // staged tables visible
+  auto buf = [&](int i) { return &lds[i * CP + col]; };
   fft<NZ, -1>(v, t, act, buf, rz);
   if (act) {
     const int ky = gc / a.NXH, kx = gc - ky * a.NXH;

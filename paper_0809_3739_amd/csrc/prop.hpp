@@ -9,21 +9,37 @@ constexpr int MAX_K = 6;  // order 2K <= 12
 enum PlaneMode { PM_FWD = 0, PM_LINK = 1, PM_TAIL = 2, PM_HTAIL = 3 };
 enum PencilKind { PK_EXP = 0, PK_ADD = 1 };
 
+// Per-state addresses for launches that cover states of several systems of
+// one grid (batched uneven systems).  One entry per state of the launch.
+struct StateDesc {
+  const void* real_in;        // states (PM_FWD) or phi (PM_HTAIL)
+  void* real_out;             // PM_TAIL / PM_HTAIL output
+  void* spec;                 // this state's chain-0 half spectrum
+  const void* fac;            // the state's system: base of its factor-table set
+  const void* V;              // the state's system: potential in the data type (PM_HTAIL)
+  const void* kin;            // the state's system: kinetic exp tables of chain 0
+  const void* hk;             // the state's system: additive kinetic tables (H)
+  long chain_stride;          // elements between consecutive chains' spectra
+};
+
 // One plane-pass launch.  Pointers are device addresses; element types are the
 // plan's data type F (float or double) for real arrays and cx<F> for spectra.
+// Without desc, state s of the launch sits at base + (state0 + s) * stride.
 struct PlaneArgs {
   const void* real_in;        // PM_FWD: states; PM_HTAIL: the phi of V*phi
-  const void* spec_in;        // PM_LINK, PM_HTAIL: half spectra; PM_TAIL: chain 1 half spectra
-  void* spec_out;             // PM_FWD, PM_LINK
+  void* spec;                 // half spectra of this launch's chain (PM_TAIL: chain 1)
   void* real_out;             // PM_TAIL, PM_HTAIL
-  const void* fac;            // pointwise factor table [z][y][x] (PM_TAIL: base of the table set)
+  const void* fac;            // factor-table set [2K][z][y][x] (PM_HTAIL: V)
   const void* rx;             // roots of unity, length NX/2
   const void* ry;             // roots of unity, length NY
   const void* wpost;          // exp(-2 pi i k / NX), k = 0..NX/4
+  const StateDesc* desc;      // optional per-state addresses (batched launches)
   long real_state_stride;     // elements between consecutive states (real arrays)
   long spec_state_stride;     // elements between consecutive states (spectra)
   long chain_stride;          // PM_TAIL: elements between the chains' spectra
-  long fac_table_stride;      // PM_TAIL: elements between consecutive factor tables
+  long fac_table_stride;      // elements between consecutive factor tables (= N)
+  int fac_index;              // PM_FWD / PM_LINK: factor table used, -1 for none
+  int chain;                  // desc mode: chain of this launch
   int state0;                 // first state of this launch
   int K;                      // PM_TAIL: number of chains
   double coef[MAX_K];         // PM_TAIL: c_1..c_K
@@ -32,13 +48,15 @@ struct PlaneArgs {
 struct PencilArgs {
   void* data;                 // half spectra, in place
   const void* rz;             // roots of unity, length NZ
-  const void* tx;             // per-axis tables (kx, ky, kz) in the data type
-  const void* ty;
-  const void* tz;
+  const void* tab;            // per-axis tables [kx | ky | kz] in the data type
+  const StateDesc* desc;      // optional per-state addresses
   long state_stride;          // elements between states = NZ * M
   int M;                      // columns per z = NY * NXH
   int NXH;                    // NX/2 + 1
+  int NY;
   int state0;
+  int chain;                  // desc mode: chain of this launch
+  int desc_tables;            // desc mode: 0 = exp tables of `chain`, 1 = additive tables
 };
 
 bool plane_supported(int is_double, int nx, int ny);

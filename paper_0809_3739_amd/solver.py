@@ -123,6 +123,15 @@ class Plan:
                                          _dptr(out["re"]), _dptr(out["re_perp"])))
         return out
 
+    def small_dense_phases(self) -> dict:
+        us = np.zeros(5)
+        self._check(self.lib.mpe_small_dense_phases(self.h, _dptr(us)))
+        return dict(zip(("cholesky", "tri_solves", "jacobi", "rebuild", "back_subst"), us.tolist()))
+
+    @property
+    def last_jacobi_sweeps(self) -> int:
+        return int(self.lib.mpe_last_jacobi_sweeps(self.h))
+
     def set_graph(self, on: bool):
         self._check(self.lib.mpe_set_graph(self.h, 1 if on else 0))
 
@@ -137,6 +146,88 @@ class Plan:
         cnt = (C.c_int64 * len(_lib.KERNEL_CLASSES))()
         self._check(self.lib.mpe_get_kernel_times(self.h, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
+
+class Batch:
+    """Many independent systems advanced together (one order and precision).
+
+    ``systems``: objects with ``grid``, ``box``, ``V`` (float64 [nz][ny][nx]) and
+    ``n_states``; ``n_guard`` is added to every system.  State blocks are torch
+    tensors, one per system, shaped (m_i, nz, ny, nx).
+    """
+
+    def __init__(self, systems, order: int, precision: str = "fp32", n_guard: int = 0,
+                 hbar2_over_m: float = 1.0, stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmpe needs a HIP device")
+        self.lib = _lib.lib()
+        self.order, self.precision, self.dtype = int(order), precision, DTYPES[precision]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._V = [torch.as_tensor(np.ascontiguousarray(sy.V)).to("cuda", torch.float64).contiguous()
+                   for sy in systems]
+        descs = (_lib.SystemDesc * len(systems))()
+        self.shapes = []
+        for i, sy in enumerate(systems):
+            d = descs[i]
+            for a in range(3):
+                d.grid[a] = int(sy.grid[a])
+                d.box[a] = float(sy.box[a])
+            d.n_states, d.n_guard = int(sy.n_states), int(n_guard)
+            d.V = self._V[i].data_ptr()
+            self.shapes.append((int(sy.n_states) + n_guard, int(sy.grid[2]), int(sy.grid[1]), int(sy.grid[0])))
+        h = C.c_void_p()
+        code = self.lib.mpe_batch_create(C.byref(h), len(systems), descs, self.order, PRECISIONS[precision],
+                                         float(hbar2_over_m), C.c_void_p(self.stream.cuda_stream))
+        _lib.check(code)
+        self.h = h
+        self.count = len(systems)
+        self.m = [s[0] for s in self.shapes]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mpe_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, code):
+        if code != _lib.MPE_OK:
+            raise _lib.MpeError(code, self.lib.mpe_batch_last_error(self.h).decode())
+
+    def new_states(self, i: int, data=None) -> torch.Tensor:
+        if data is None:
+            return torch.zeros(self.shapes[i], dtype=self.dtype, device="cuda")
+        return torch.as_tensor(np.ascontiguousarray(data)).to("cuda", self.dtype).reshape(self.shapes[i]).contiguous()
+
+    def _ptrs(self, psis):
+        if len(psis) != self.count:
+            raise ValueError("one state block per system")
+        for t, shp in zip(psis, self.shapes):
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == self.dtype and tuple(t.shape) == shp):
+                raise ValueError(f"state block must be a contiguous {self.dtype} CUDA tensor of shape {shp}")
+        return (C.c_void_p * self.count)(*[t.data_ptr() for t in psis])
+
+    def step(self, psis, dt: float):
+        self._check(self.lib.mpe_batch_step(self.h, self._ptrs(psis), float(dt)))
+
+    def iterate(self, psis, dt: float):
+        tot = sum(self.m)
+        out = {k: np.zeros(tot) for k in ("eig", "rh", "re", "re_perp")}
+        self._check(self.lib.mpe_batch_iterate(self.h, self._ptrs(psis), float(dt), _dptr(out["eig"]),
+                                               _dptr(out["rh"]), _dptr(out["re"]), _dptr(out["re_perp"])))
+        res, off = [], 0
+        for mi in self.m:
+            res.append({k: v[off:off + mi].copy() for k, v in out.items()})
+            off += mi
+        return res
+
+    @property
+    def launches_per_step(self) -> int:
+        return int(self.lib.mpe_batch_launches_per_step(self.h))
 
 
 # ------------------------------------------------------------------ step-size protocol

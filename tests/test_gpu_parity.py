@@ -323,3 +323,38 @@ def test_graph_replay_matches_eager(P):
     for a, b in zip(runs[0], runs[1]):
         for x, y in zip(a, b):
             assert np.array_equal(x, y)
+
+
+def test_batch_matches_individual_plans(P):
+    """Uneven systems advanced as one batch equal separately planned systems bitwise
+    (batched propagation launches over several systems, one graph per iteration)."""
+    systems = [W.random_molecule(s, grids=(32, 48), n_states=(4, 12)) for s in (11, 12, 13, 14, 15)]
+    say("batch vs individual", [(sy.grid[0], sy.n_states) for sy in systems])
+    batch = P.Batch(systems, 8, "fp32")
+    psis_b, plans, psis_i = [], [], []
+    for i, sy in enumerate(systems):
+        x0 = W.random_states(100 + i, sy.n_states, sy.grid)
+        psis_b.append(batch.new_states(i, x0))
+        pl = P.Plan(sy.grid, sy.box, sy.n_states, 8, "fp32")
+        pl.set_potential(sy.V)
+        plans.append(pl)
+        psis_i.append(pl.new_states(x0))
+        pl.orthonormalize(psis_i[-1])
+        pl.set_graph(False)
+    # the same orthonormalisation as the individual plans
+    for i in range(len(systems)):
+        psis_b[i].copy_(psis_i[i])
+    for it, dt in enumerate((0.2, 0.2, 0.1)):
+        outs = batch.iterate(psis_b, dt)
+        for i, pl in enumerate(plans):
+            r = pl.iterate(psis_i[i], dt)
+            assert np.array_equal(outs[i]["eig"], r["eig"]), (it, i)
+            assert np.array_equal(outs[i]["rh"], r["rh"]), (it, i)
+            assert np.array_equal(psis_b[i].cpu().numpy(), psis_i[i].cpu().numpy()), (it, i)
+    say("  launches per batched iteration", batch.launches_per_step)
+    # the in-place batched step equals each plan's mpe_step
+    for i, pl in enumerate(plans):
+        pl.step(psis_i[i], 0.3)
+    batch.step(psis_b, 0.3)
+    for i in range(len(systems)):
+        assert np.array_equal(psis_b[i].cpu().numpy(), psis_i[i].cpu().numpy())
