@@ -206,6 +206,86 @@ mpe_status mpe_batch_iterate(mpe_batch b, void* const* psi, double dt, double* e
 /* Kernel launches in the captured iteration graph (diagnostic). */
 int32_t mpe_batch_launches_per_step(mpe_batch b);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start (an addition outside the paper, whose Section III starts
+ * from random or plane-wave states): a small 3-D U-Net maps a coarse potential
+ * on a d^3 grid (d = 32 for the cage workload) to n_out starting orbitals on
+ * the same grid; wsn_upsample_periodic carries them to the solver's grid,
+ * after which the solver's own residual R^H judges them.  The network is
+ * trained on the GPU with these calls.
+ *
+ * Architecture: channels 16/32/64 over three levels (d, d/2, d/4); every
+ * convolution has 3x3x3 periodic taps, weights W[co][tz][ty][tx][ci] and a
+ * bias; ReLU after every convolution but the head; two stride-2 convolutions
+ * down, nearest-neighbour doubling plus channel concatenation up:
+ *   e1 = relu(c1b(relu(c1a(v))))  e2 = relu(c2b(relu(c2a_s2(e1))))
+ *   e3 = relu(c3b(relu(c3a_s2(e2))))  d2 = relu(cd2([up(e3) | e2]))
+ *   d1 = relu(cd1([up(d2) | e1]))     y = head(d1)
+ * Parameters form one float32 vector, layer by layer (c1a, c1b, c2a, c2b,
+ * c3a, c3b, d2, d1, head), each layer's weights [co][27][ci] then its bias.
+ * Convolutions run on bfloat16 MFMA with float32 accumulation (operands
+ * rounded to bfloat16, float32 master weights).
+ * ------------------------------------------------------------------------- */
+typedef struct wsn_net_s* wsn_net;
+
+/* Create a network for d = grid (a multiple of 4, >= 8), n_out output orbitals
+ * (a multiple of 8, <= 128), batches up to max_batch; He-normal weights drawn
+ * from seed, zero biases, zero Adam moments.  All device memory (weights,
+ * activations for max_batch, gradients) is allocated here and owned by the
+ * network.  hip_stream may be NULL (default stream). */
+mpe_status wsn_create(wsn_net* out, int32_t grid, int32_t n_out, int32_t max_batch, uint64_t seed,
+                      void* hip_stream);
+mpe_status wsn_destroy(wsn_net n);
+const char* wsn_last_error(wsn_net n);
+
+/* Length of the parameter vector (-1 for a null network). */
+int64_t wsn_num_params(wsn_net n);
+
+/* Copy the parameters (which = 0) or the accumulated gradients (which = 1) to
+ * host float32 [wsn_num_params]; synchronises. */
+mpe_status wsn_get_params(wsn_net n, float* host, int32_t which);
+/* Replace the parameters from host float32 [wsn_num_params]; synchronises. */
+mpe_status wsn_set_params(wsn_net n, const float* host);
+/* Clear the accumulated gradients. */
+mpe_status wsn_zero_grads(wsn_net n);
+
+/* Forward pass.  v: device float32 [batch][d][d][d] potentials, multiplied by
+ * vscale on input; y: device float32 [batch][n_out][d][d][d] orbitals (state
+ * layout, z slowest), the head's output multiplied by yscale.  Keeps the
+ * activations (and yscale) for wsn_backward.  MPE_ERR_INVALID_ARGUMENT for a
+ * batch outside [1, max_batch]. */
+mpe_status wsn_forward(wsn_net n, const float* v, float vscale, float yscale, int32_t batch, float* y);
+
+/* Backward pass of the last forward: dy is device float32 shaped like y
+ * (dL/dy); parameter gradients are ADDED to the accumulated ones.
+ * MPE_ERR_STATE before any forward. */
+mpe_status wsn_backward(wsn_net n, const float* dy);
+
+/* Adam step with bias correction (t = 1, 2, ...) on the accumulated
+ * gradients, which it then clears. */
+mpe_status wsn_adam_step(wsn_net n, float lr, float beta1, float beta2, float eps, int32_t t);
+
+/* Rotation-invariant subspace loss of one prediction y (device float32
+ * [n_states][P]) against targets (device float32 [n_states][P]): with
+ * M = y target^T,
+ *   L = ||y - M target||^2 + ||M M^T - I||^2,
+ * zero exactly when y = R target with R orthogonal and orthonormal targets.
+ * Writes into dy (device, same shape; must not alias y) the gradient
+ * 2(y - M target) + 4(M M^T - I) M target, which is dL/dy when the target
+ * rows are orthonormal (the intended use), and, when loss_host is not NULL,
+ * {L, ||M M^T - I||^2} into loss_host[2].  Overlaps and M are float64
+ * (||y - M target||^2 = ||y||^2 - 2||M||^2 + tr(M target target^T M^T)).
+ * Synchronises. */
+mpe_status wsn_subspace_loss(wsn_net n, const float* y, const float* target, int32_t n_states, int64_t P,
+                             double* loss_host, float* dy);
+
+/* Periodic trilinear interpolation of u (device float32 [channels][d][d][d])
+ * onto the grid of (d*factor)^3 points: fine point j of an axis sits at coarse
+ * coordinate j/factor.  out: device float32 [channels][D][D][D], D = d*factor.
+ * Enqueued on hip_stream (may be NULL). */
+mpe_status wsn_upsample_periodic(const float* u, int32_t channels, int32_t d, int32_t factor, float* out,
+                                 void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,18 @@ SIGNATURES = {
     "mpe_batch_step": (C.c_int, [_vp, C.POINTER(_vp), C.c_double]),
     "mpe_batch_iterate": (C.c_int, [_vp, C.POINTER(_vp), C.c_double, _dp, _dp, _dp, _dp]),
     "mpe_batch_launches_per_step": (C.c_int32, [_vp]),
+    "wsn_create": (C.c_int, [C.POINTER(_vp), _i32, _i32, _i32, C.c_uint64, _vp]),
+    "wsn_destroy": (C.c_int, [_vp]),
+    "wsn_last_error": (C.c_char_p, [_vp]),
+    "wsn_num_params": (C.c_int64, [_vp]),
+    "wsn_get_params": (C.c_int, [_vp, _vp, _i32]),
+    "wsn_set_params": (C.c_int, [_vp, _vp]),
+    "wsn_zero_grads": (C.c_int, [_vp]),
+    "wsn_forward": (C.c_int, [_vp, _vp, C.c_float, C.c_float, _i32, _vp]),
+    "wsn_backward": (C.c_int, [_vp, _vp]),
+    "wsn_adam_step": (C.c_int, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _i32]),
+    "wsn_subspace_loss": (C.c_int, [_vp, _vp, _vp, _i32, C.c_int64, _dp, _vp]),
+    "wsn_upsample_periodic": (C.c_int, [_vp, _i32, _i32, _i32, _vp, _vp]),
 }
 
 

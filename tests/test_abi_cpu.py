@@ -21,7 +21,7 @@ LIBPATH = os.path.join(ROOT, "paper_0809_3739_amd", "libmpe.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mpe_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:mpe|wsn)_[a-z_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -96,3 +96,14 @@ def test_plan_create_argument_validation(lib):
 def test_status_strings(lib):
     for code in range(9):
         assert lib.mpe_status_string(code)
+
+
+def test_warm_start_net_rejects_bad_shapes_before_device_work(lib):
+    h = C.c_void_p()
+    for grid, n_out, batch in [(6, 8, 1), (30, 8, 1), (32, 12, 1), (32, 136, 1), (32, 8, 0)]:
+        assert lib.wsn_create(C.byref(h), grid, n_out, batch, 0, None) == 1, (grid, n_out, batch)
+        assert not h.value
+    assert lib.wsn_num_params(None) == -1
+    assert lib.wsn_destroy(None) == 1
+    assert lib.wsn_last_error(None) == b"null network"
+    assert lib.wsn_upsample_periodic(None, 1, 4, 2, None, None) == 1

@@ -174,3 +174,9 @@ def jittered_c60_centers(seed: int, radius: float = 6.7, jitter: float = 0.2) ->
     c = truncated_icosahedron(radius) + rng.normal(0.0, jitter, (60, 3))
     v0 = float(rng.uniform(1.0, 1.4))
     return c, v0
+
+
+def jittered_c60_potential(seed: int, grid: int, box: float = 32.0, sigma: float = 0.9) -> np.ndarray:
+    """C60-like cage of jittered_c60_centers(seed) on a grid^3 mesh of the cubic box, float64."""
+    centers, v0 = jittered_c60_centers(seed)
+    return gaussian_wells((grid,) * 3, (box,) * 3, centers, v0, sigma)
