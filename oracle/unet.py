@@ -23,6 +23,12 @@ Conventions (shared with the GPU implementation by specification only):
   states T (n x P, orthonormal rows): with M = Y T^T,
     L = ||Y - M T||^2 + ||M M^T - I||^2,
   zero exactly when Y = R T with R orthogonal; dL/dY = 2(Y - M T) + 4 (M M^T - I) M T.
+  This loss has a stationary point at Y = 0 (its gradient vanishes with M).
+* Procrustes loss (used for training): with the polar factor Q = U V^T of
+  M = U Sigma V^T,  L_P = ||Y - Q T||^2, the distance from Y to the nearest
+  rotation of the targets (the orthogonal Procrustes problem, for orthonormal
+  T); dL_P/dY = 2 (Y - Q T) wherever M has full rank (the derivative of the
+  nuclear norm of M is Q).  Its gradient never vanishes away from the minimum.
 """
 from __future__ import annotations
 
@@ -163,6 +169,15 @@ def subspace_loss(Y: np.ndarray, T: np.ndarray):
     L = float(np.sum(R1 * R1) + np.sum(G * G))
     dY = 2.0 * R1 + 4.0 * (G @ M) @ T
     return L, dY
+
+
+def procrustes_loss(Y: np.ndarray, T: np.ndarray):
+    """L = ||Y - Q T||^2 with Q the polar factor of M = Y T^T; returns (L, dL/dY, sum of singular values)."""
+    M = Y @ T.T
+    U, sig, Vt = np.linalg.svd(M)
+    Q = U @ Vt
+    R = Y - Q @ T
+    return float(np.sum(R * R)), 2.0 * R, float(np.sum(sig))
 
 
 def orbitals_from_output(y: np.ndarray) -> np.ndarray:

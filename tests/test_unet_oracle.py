@@ -119,6 +119,36 @@ def test_subspace_loss_minimum_and_gradient():
     assert abs(unet.subspace_loss(Y, Q @ T)[0] - L) < 1e-9 * L
 
 
+def test_procrustes_loss_is_the_distance_to_the_nearest_rotation():
+    import scipy.linalg as sla
+    rng = np.random.default_rng(9)
+    n, P = 6, 50
+    T = np.linalg.qr(rng.standard_normal((P, n)))[0].T
+    Y = rng.standard_normal((n, P))
+    L, dY, nuc = unet.procrustes_loss(Y, T)
+    # SciPy solves min_R ||R A - B|| over orthogonal R (as A^T R^T = B^T): A = T, B = Y
+    R, _ = sla.orthogonal_procrustes(T.T, Y.T)
+    assert abs(L - np.sum((Y - R.T @ T) ** 2)) < 1e-10 * L
+    for _ in range(20):                                   # no rotation does better
+        Qr = np.linalg.qr(rng.standard_normal((n, n)))[0]
+        assert np.sum((Y - Qr @ T) ** 2) >= L - 1e-10
+    # closed form through the nuclear norm, and the special cases
+    assert abs(L - (np.sum(Y * Y) + n - 2 * nuc)) < 1e-10 * L
+    R0 = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    L0, g0, _ = unet.procrustes_loss(R0 @ T, T)
+    assert L0 < 1e-24 and np.abs(g0).max() < 1e-11
+    Qrot = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    assert abs(unet.procrustes_loss(Y, Qrot @ T)[0] - L) < 1e-10 * L
+    h = 1e-6
+    for _ in range(8):
+        i = (rng.integers(0, n), rng.integers(0, P))
+        Yp, Ym = Y.copy(), Y.copy()
+        Yp[i] += h
+        Ym[i] -= h
+        fd = (unet.procrustes_loss(Yp, T)[0] - unet.procrustes_loss(Ym, T)[0]) / (2 * h)
+        assert abs(fd - dY[i]) < 1e-5 * max(1.0, abs(fd))
+
+
 def test_trilinear_upsample_matches_map_coordinates():
     rng = np.random.default_rng(7)
     u = rng.standard_normal((2, 6, 6, 6))
