@@ -85,7 +85,12 @@ def main():
     ap.add_argument("--dt", type=float, default=0.5)
     ap.add_argument("--states-per-launch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--solve", action="store_true", help="also time a full solve to max R^H <= 1e-8")
+    ap.add_argument("--solve", action="store_true",
+                    help="also time a full solve to max R^H <= 1e-8 from a random start (float32 iterations, "
+                         "float64 once float32 stalls)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before timing, run a plain copy kernel over MIB MiB three times (counter calibration "
+                         "for rocprofv3 --pmc runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -106,6 +111,13 @@ def main():
         plan.set_states_per_launch(args.states_per_launch)
     psi = plan.new_states(W.random_states(0, m, s.grid))
     plan.orthonormalize(psi)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)     # one read and one write of the buffer
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         plan.iterate(psi, args.dt)
     torch.cuda.synchronize()
@@ -131,13 +143,11 @@ def main():
     dom = max(prop, key=lambda k: kt[k][0])
     avg_ms = kt[dom][0] / kt[dom][1]
     ach = prop_bytes_per_launch(dom, s.grid, m, K, fsz) / (avg_ms * 1e-3) / 1e9
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_c60_{args.grid}_{args.precision}.json")
-    if os.path.exists(tf):
-        try:
-            traffic = json.load(open(tf)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    from paper_0809_3739_amd.rocprof_summary import read_traffic
+    # measured HBM bytes per launch (counter runs) over the same launch duration, in the unit of `achieved`
+    traffic_bytes = read_traffic(os.path.join(ROOT, "profiles",
+                                              f"traffic_{dom}_c60_{args.grid}_{args.precision}.txt"))
+    traffic = None if traffic_bytes is None else round(traffic_bytes / 1e9 / (avg_ms * 1e-3), 1)
     result = {
         "metric": "FFT-propagate HBM GB/s (s to 120 states at resid 1e-8, learned vs plain start; "
                   "FFT-propagate HBM GB/s)",
@@ -160,15 +170,19 @@ def main():
                                **{k: round(v[0] / args.steps, 3) for k, v in kt.items() if v[1]}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": prop_bytes_per_launch(dom, s.grid, m, K, fsz),
+                     "traffic_bytes_per_launch": traffic_bytes,
                      "avg_launch_ms": round(avg_ms, 4)},
         "last_iteration": {"eig0": float(out["eig"][0]), "eig119": float(out["eig"][119]),
                            "max_rh": float(np.max(out["rh"][:n_states]))},
     }
     if args.solve:
+        plan64 = P.Plan(s.grid, s.box, n_states, args.order, "fp64", n_guard=n_guard)
+        plan64.set_potential(s.V)
         psi2 = plan.new_states(W.random_states(7, m, s.grid))
-        res = P.solve(plan, psi2, dt0=0.5, gamma=1e-8, n_check=n_states)
+        res = P.solve_ladder(plan, plan64, psi2, dt0=0.5, gamma=1e-8, n_check=n_states)
         result["solve"] = {"seconds": round(res.seconds, 3), "iterations": res.iterations, "levels": res.levels,
-                           "converged": res.converged, "final_dt": res.dt, "start": "random"}
+                           "converged": res.converged, "final_dt": res.dt, "start": "random", "stages": res.stages}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(s, K, fsz)
     print(json.dumps(result))

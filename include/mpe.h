@@ -279,6 +279,20 @@ mpe_status wsn_adam_step(wsn_net n, float lr, float beta1, float beta2, float ep
 mpe_status wsn_subspace_loss(wsn_net n, const float* y, const float* target, int32_t n_states, int64_t P,
                              double* loss_host, float* dy);
 
+/* Procrustes loss of one prediction y (device float32 [n_states][P]) against
+ * targets with orthonormal rows (device float32 [n_states][P]): with M =
+ * y target^T and its polar factor Q = M (M^T M)^(-1/2),
+ *   L = ||y - Q target||^2,
+ * the distance from y to the nearest rotation of the targets.  Writes
+ * dL/dy = 2(y - Q target) into dy (device, same shape; must not alias y) and,
+ * when loss_host is not NULL, {L, sum of the singular values of M} into
+ * loss_host[2].  Overlaps, M^T M, its eigenpairs (the plan's Jacobi solver)
+ * and Q are float64; eigenvalues below 1e-12 of the largest are raised to it.
+ * MPE_ERR_EIG_NO_CONVERGENCE / MPE_ERR_NONFINITE when the eigenpairs fail.
+ * Synchronises. */
+mpe_status wsn_procrustes_loss(wsn_net n, const float* y, const float* target, int32_t n_states, int64_t P,
+                               double* loss_host, float* dy);
+
 /* Periodic trilinear interpolation of u (device float32 [channels][d][d][d])
  * onto the grid of (d*factor)^3 points: fine point j of an axis sits at coarse
  * coordinate j/factor.  out: device float32 [channels][D][D][D], D = d*factor.

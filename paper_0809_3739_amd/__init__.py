@@ -5,6 +5,6 @@ Hot path in hand-written HIP for gfx950 behind the C ABI of ``include/mpe.h``
 ``Plan`` over torch device tensors and the step-size driver.
 """
 from ._lib import MpeError, coefficients, lib  # noqa: F401
-from .solver import Batch, Plan, SolveResult, solve  # noqa: F401
+from .solver import Batch, Plan, SolveResult, solve, solve_ladder  # noqa: F401
 
-__all__ = ["Plan", "Batch", "solve", "SolveResult", "coefficients", "MpeError", "lib"]
+__all__ = ["Plan", "Batch", "solve", "solve_ladder", "SolveResult", "coefficients", "MpeError", "lib"]

@@ -71,6 +71,7 @@ SIGNATURES = {
     "wsn_backward": (C.c_int, [_vp, _vp]),
     "wsn_adam_step": (C.c_int, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _i32]),
     "wsn_subspace_loss": (C.c_int, [_vp, _vp, _vp, _i32, C.c_int64, _dp, _vp]),
+    "wsn_procrustes_loss": (C.c_int, [_vp, _vp, _vp, _i32, C.c_int64, _dp, _vp]),
     "wsn_upsample_periodic": (C.c_int, [_vp, _i32, _i32, _i32, _vp, _vp]),
 }
 

@@ -60,7 +60,11 @@ struct PlaneOcc {
   static constexpr int LDS = NX * plane_srow<NX>() * 2 * (int)sizeof(F);
   static constexpr int WG = (160 * 1024 / LDS) < 1 ? 1 : (160 * 1024 / LDS);
   static constexpr int W = WG * (PlaneShape<NX>::BLOCK / 64) / 4;
-  static constexpr int value = W < 1 ? 1 : (W > 8 ? 8 : W);
+  // register floor: at least 128 VGPRs (float) / 256 (double) per lane, the
+  // working set of a row or column transform plus its twiddles and addresses
+  // (a one-lane row transform, as for NX = 48, holds a whole row: half that)
+  static constexpr int WMAX = (sizeof(F) == 4 ? 4 : 2) / (Plan<NX / 2>::T == 1 ? 2 : 1);
+  static constexpr int value = W < 1 ? 1 : (W > WMAX ? WMAX : W);
 };
 
 template <typename F, int NX, int MODE>
@@ -87,6 +91,7 @@ void plane_kernel(PlaneArgs a) {
   constexpr bool ROWWAVE = (64 % TX == 0);
   static_assert(NCF * TY <= BLOCK, "one column round");
   static_assert(NCF % 2 == 0, "column pairs");
+  constexpr bool TAIL_PREFETCH = sizeof(F) == 4 && EY <= 16;
 
   __shared__ cx<F> lds[NY * SROW];
   // twiddle tables staged in LDS (they sit on the FFT critical path)
@@ -319,9 +324,10 @@ void plane_kernel(PlaneArgs a) {
       const F* __restrict__ fac = facb + (long)(2 * k + 1) * a.fac_table_stride + z_real;
       const double ck = a.coef[k];
       column_inverse_regs(vc);
-      // (float64 planes have no registers to spare for the prefetch)
+      // (float64 planes, and float32 planes with 24-element columns, have no
+      // registers to spare for the prefetch)
       if (k + 1 < a.K) {
-        if constexpr (sizeof(F) == 4) {
+        if constexpr (TAIL_PREFETCH) {
           column_load(spec0 + (long)(k + 1) * chain_stride, vc);
         }
       }
@@ -347,7 +353,7 @@ void plane_kernel(PlaneArgs a) {
         }
       }
       __syncthreads();
-      if constexpr (sizeof(F) != 4) {
+      if constexpr (!TAIL_PREFETCH) {
         if (k + 1 < a.K) column_load(spec0 + (long)(k + 1) * chain_stride, vc);
       }
     }

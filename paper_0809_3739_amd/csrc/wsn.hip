@@ -386,6 +386,85 @@ __global__ __launch_bounds__(1024) void loss_small_kernel(const double* M, const
   }
 }
 
+// A = M^T M (n x n in an mp x mp buffer, zero padded); Sid = identity
+__global__ __launch_bounds__(256) void ata_kernel(const double* M, int n, int mp, double* A, double* Sid) {
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < mp * mp; e += gridDim.x * 256) {
+    const int i = e / mp, j = e % mp;
+    double s = 0.0;
+    if (i < n && j < n)
+      for (int k = 0; k < n; ++k) s += M[(long)k * mp + i] * M[(long)k * mp + j];
+    A[e] = s;
+    Sid[e] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+// Polar factor Q = M U diag(theta)^(-1/2) U^T from the eigenpairs (theta, U) of
+// M^T M (U's columns in an mp x mp buffer), then
+//   loss = {||Y||^2 - 2 tr(Q^T M) + tr(Q S Q^T), sum_k sqrt(theta_k)}
+// and Bt[j][i] = -2 Q[i][j] (the rotation kernel then forms -2 Q T).
+// One work-group; W and Q in global scratch (visible after the barriers).
+__global__ __launch_bounds__(1024) void polar_kernel(const double* M, const double* S, const double* U,
+                                                     const double* theta, const int* status, int n, int mp,
+                                                     const double* y2, double* W, double* Q, double* Bt,
+                                                     double* loss) {
+  __shared__ double red[1024];
+  __shared__ double isq[mpe::MAXM];
+  const int tid = threadIdx.x;
+  if (status[0] != 0) {
+    if (tid == 0) loss[0] = loss[1] = __builtin_nan("");
+    return;
+  }
+  double tmax = 0.0;
+  for (int k = 0; k < n; ++k) tmax = fmax(tmax, theta[k]);
+  const double floor_ = 1e-12 * tmax;
+  double nuc = 0.0;
+  for (int k = tid; k < n; k += 1024) {
+    const double t = fmax(theta[k], floor_);
+    isq[k] = 1.0 / sqrt(t);
+  }
+  if (tid == 0)
+    for (int k = 0; k < n; ++k) nuc += sqrt(fmax(theta[k], 0.0));
+  __syncthreads();
+  for (int e = tid; e < n * n; e += 1024) {   // W = M U diag(theta^-1/2)
+    const int i = e / n, k = e % n;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += M[(long)i * mp + j] * U[(long)j * mp + k];
+    W[e] = s * isq[k];
+  }
+  __syncthreads();
+  double tqm = 0.0;
+  for (int e = tid; e < n * n; e += 1024) {   // Q = W U^T
+    const int i = e / n, j = e % n;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += W[i * n + k] * U[(long)j * mp + k];
+    Q[e] = s;
+    tqm += s * M[(long)i * mp + j];
+  }
+  __syncthreads();
+  double tqsq = 0.0;
+  for (int e = tid; e < mp * mp; e += 1024) {
+    const int i = e / mp, j = e % mp;
+    double b = 0.0;
+    if (i < n && j < n) {
+      b = -2.0 * Q[i * n + j];
+      double qs = 0.0;
+      for (int l = 0; l < n; ++l) qs += S[(long)j * mp + l] * Q[i * n + l];
+      tqsq += Q[i * n + j] * qs;
+    }
+    Bt[(long)j * mp + i] = b;
+  }
+  red[tid] = tqsq - 2.0 * tqm;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    loss[0] = y2[0] + red[0];
+    loss[1] = nuc;
+  }
+}
+
 __global__ void sumsq_kernel(const float* y, long n, double* out) {
   __shared__ double red[256];
   double s = 0.0;
@@ -573,6 +652,10 @@ mpe_status wsn_create(wsn_net* out, int32_t grid, int32_t n_out, int32_t max_bat
   n->n_out = n_out;
   n->max_batch = max_batch;
   n->st = reinterpret_cast<hipStream_t>(hip_stream);
+  if (mpe::prepare_small_dense() != hipSuccess) {
+    delete n;
+    return MPE_ERR_DEVICE;
+  }
   struct Spec { const char* name; int ci, co, stride, relu, ci_pad; };
   const Spec spec[] = {{"c1a", 1, 16, 1, 1, 8},   {"c1b", 16, 16, 1, 1, 16}, {"c2a", 16, 32, 2, 1, 16},
                        {"c2b", 32, 32, 1, 1, 32}, {"c3a", 32, 64, 2, 1, 32}, {"c3b", 64, 64, 1, 1, 64},
@@ -618,8 +701,9 @@ mpe_status wsn_create(wsn_net* out, int32_t grid, int32_t n_out, int32_t max_bat
        alloc((void**)&n->g_a3, B * v8 * 64 * 4) && alloc((void**)&n->g_e2, B * v16 * 32 * 4) &&
        alloc((void**)&n->g_a2, B * v16 * 32 * 4) && alloc((void**)&n->g_e1, B * v32 * 16 * 4) &&
        alloc((void**)&n->g_a1, B * v32 * 16 * 4);
-  // loss scratch: gram partials (2 products x <= 128 chunks), M and S, B^T, G, loss values
-  n->scratch_bytes = ((size_t)256 * 128 * 128 + 4 * 128 * 128 + 16) * sizeof(double);
+  // loss scratch: gram partials (2 products x <= 128 chunks), M and S, B^T, G (then W), A, Sid, L, rot, U, Q,
+  // theta, small-dense scratch, status, loss values
+  n->scratch_bytes = ((size_t)256 * 128 * 128 + 11 * 128 * 128 + 128 + 256 + 16 + 16) * sizeof(double);
   ok = ok && alloc((void**)&n->scratch, n->scratch_bytes);
   if (!ok) {
     wsn_destroy(n);
@@ -792,6 +876,102 @@ mpe_status wsn_subspace_loss(wsn_net n, const float* y, const float* target, int
   double lh[2];
   WHIP(n, hipMemcpyAsync(lh, lv + 1, sizeof lh, hipMemcpyDeviceToHost, n->st));
   WHIP(n, hipStreamSynchronize(n->st));
+  if (loss_host) {
+    loss_host[0] = lh[0];
+    loss_host[1] = lh[1];
+  }
+  return MPE_OK;
+}
+
+mpe_status wsn_procrustes_loss(wsn_net n, const float* y, const float* target, int32_t n_states, int64_t P,
+                               double* loss_host, float* dy) {
+  if (!n || !y || !target || !dy || n_states < 1 || n_states > mpe::MAXM || P < 1)
+    return MPE_ERR_INVALID_ARGUMENT;
+  if ((const float*)dy == y) return wfail(n, MPE_ERR_INVALID_ARGUMENT, "dy must not alias y");
+  const int mp = (n_states + 15) / 16 * 16;
+  long nch = std::min<long>(128, std::max<long>(1, (P + 4095) / 4096));
+  long chunk = ((P + nch - 1) / nch + 31) / 32 * 32;
+  nch = (P + chunk - 1) / chunk;
+  const long q = 128L * 128;
+  double* partials = n->scratch;   // [2][nch][mp][mp]
+  double* M = partials + 256 * q;  // M then S
+  double* S = M + (long)mp * mp;
+  double* Bt = M + 2 * q;
+  double* W = Bt + q;
+  double* A = W + q;
+  double* Sid = A + q;
+  double* Lb = Sid + q;
+  double* rot = Lb + q;
+  double* U = rot + q;
+  double* Q = U + q;
+  double* theta = Q + q;
+  double* sds = theta + 128;
+  int* status = reinterpret_cast<int*>(sds + 256);
+  double* lv = sds + 256 + 16;     // [||y||^2, loss, nuclear norm]
+  mpe::GramArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.X[0] = y;
+  g.Y[0] = target;
+  g.X[1] = target;
+  g.Y[1] = target;
+  g.partials = partials;
+  g.N = P;
+  g.chunk = chunk;
+  g.m = n_states;
+  g.mp = mp;
+  WHIP(n, mpe::launch_gram(0, g, 2, (int)nch, n->st));
+  WHIP(n, mpe::launch_reduce(partials, (int)nch, (long)mp * mp, 2, M, n->st));
+  WHIP(n, hipMemsetAsync(lv, 0, sizeof(double), n->st));
+  hipLaunchKernelGGL(sumsq_kernel, dim3(256), dim3(256), 0, n->st, y, (long)n_states * P, lv);
+  WHIP(n, hipGetLastError());
+  hipLaunchKernelGGL(ata_kernel, dim3((mp * mp + 255) / 256), dim3(256), 0, n->st, (const double*)M, n_states, mp, A,
+                     Sid);
+  WHIP(n, hipGetLastError());
+  // eigenpairs of M^T M: the plan's small dense solver with S = I (Cholesky factor I, C = U)
+  mpe::SmallDenseArgs d;
+  std::memset(&d, 0, sizeof(d));
+  d.S = Sid;
+  d.Hs = A;
+  d.L = Lb;
+  d.rot = rot;
+  d.scratch = sds;
+  d.C = U;
+  d.theta = theta;
+  d.status = status;
+  d.m = n_states;
+  d.mp = mp;
+  d.mode = mpe::SD_RR;
+  d.max_sweeps = 60;
+  d.tol = 1e-13;
+  d.pivot_tol = 1e-13;
+  WHIP(n, mpe::launch_small_dense(d, n->st));
+  hipLaunchKernelGGL(polar_kernel, dim3(1), dim3(1024), 0, n->st, (const double*)M, (const double*)S,
+                     (const double*)U, (const double*)theta, (const int*)status, n_states, mp, (const double*)lv, W,
+                     Q, Bt, lv + 1);
+  WHIP(n, hipGetLastError());
+  mpe::RotateArgs r;
+  std::memset(&r, 0, sizeof(r));
+  r.Phi = target;
+  r.C = Bt;
+  r.Psi = dy;
+  r.N = P;
+  r.status = status;
+  long rch = std::min<long>(1024, std::max<long>(1, (P + 255) / 256));
+  r.chunk = ((P + rch - 1) / rch + 63) / 64 * 64;
+  rch = (P + r.chunk - 1) / r.chunk;
+  r.m = n_states;
+  r.mp = mp;
+  WHIP(n, mpe::launch_rotate(0, false, r, (int)rch, n->st));
+  hipLaunchKernelGGL(axpy2_kernel, dim3(nblk((long)n_states * P)), dim3(256), 0, n->st, y, dy, (long)n_states * P);
+  WHIP(n, hipGetLastError());
+  double lh[2];
+  int st[2];
+  WHIP(n, hipMemcpyAsync(lh, lv + 1, sizeof lh, hipMemcpyDeviceToHost, n->st));
+  WHIP(n, hipMemcpyAsync(st, status, sizeof st, hipMemcpyDeviceToHost, n->st));
+  WHIP(n, hipStreamSynchronize(n->st));
+  if (st[0] != 0)
+    return wfail(n, st[0] == mpe::ST_NONFINITE ? MPE_ERR_NONFINITE : MPE_ERR_EIG_NO_CONVERGENCE,
+                 "eigenpairs of M^T M failed (status " + std::to_string(st[0]) + ")");
   if (loss_host) {
     loss_host[0] = lh[0];
     loss_host[1] = lh[1];

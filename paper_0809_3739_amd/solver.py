@@ -241,11 +241,14 @@ class SolveResult:
     converged: bool
     seconds: float
     history: list = field(default_factory=list)
+    stalled: bool = False
+    stages: list = field(default_factory=list)
 
 
 def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, reduce: float = 0.5,
           n_check: int | None = None, margin: float = 0.01, max_iter_per_level: int = 2000,
-          max_levels: int = 30, orthonormalize_first: bool = True, callback=None) -> SolveResult:
+          max_levels: int = 30, orthonormalize_first: bool = True, callback=None,
+          stall_window: int | None = None, stall_gain: float = 0.02, accept=None) -> SolveResult:
     """Iterate with the protocol of Section III until R^H_j < gamma for the
     first ``n_check`` states.
 
@@ -254,6 +257,16 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
     max_j R^E_perp_j <= margin * gamma * dt^2 (R^E_perp/dt^2 is on the scale
     of the part of R^H still removable at this dt); then R^H decides between
     stopping and dt <- reduce * dt with the current states as the new start.
+
+    With ``stall_window`` the solve also ends (``stalled``, not converged, dt
+    kept) when the last ``stall_window`` iterations of a level lowered the best
+    max R^H by less than the fraction ``stall_gain``: the rounding floor of the
+    plan's precision has been reached (in float32 it lies above the gamma
+    that float64 reaches, and it rises as dt shrinks, so halving would not help).
+
+    ``accept(out, iteration)``, if given, is called after every iteration; a
+    non-None return {"eig", "rh"} ends the solve as converged with those values
+    (an external, more accurate convergence check).
     """
     n_check = plan.n_states if n_check is None else n_check
     t0 = time.perf_counter()
@@ -265,20 +278,86 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
     out = None
     for level in range(max_levels):
         ge = margin * gamma * dt * dt
+        rh_level = []
         for it in range(max_iter_per_level):
             out = plan.iterate(psi, dt)
             total += 1
             rep = float(np.max(out["re_perp"][:n_check]))
             rhm = float(np.max(out["rh"][:n_check]))
+            rh_level.append(rhm)
             hist.append({"dt": dt, "it": total, "re_perp": rep, "rh": rhm, "eig0": float(out["eig"][0]),
                          "t": time.perf_counter() - t0})
             if callback:
                 callback(hist[-1])
+            if accept is not None:
+                ok = accept(out, total)
+                if ok is not None:
+                    return SolveResult(ok["eig"], ok["rh"], dt, total, level + 1, True, time.perf_counter() - t0,
+                                       hist)
             if rhm < gamma:
                 break
             if it > 0 and rep <= ge:
                 break
+            if stall_window and it >= stall_window:
+                before = min(rh_level[:-stall_window])
+                if min(rh_level[-stall_window:]) > (1.0 - stall_gain) * before:
+                    return SolveResult(out["eig"], out["rh"], dt, total, level + 1, False,
+                                       time.perf_counter() - t0, hist, stalled=True)
         if float(np.max(out["rh"][:n_check])) < gamma:
             return SolveResult(out["eig"], out["rh"], dt, total, level + 1, True, time.perf_counter() - t0, hist)
         dt *= reduce
     return SolveResult(out["eig"], out["rh"], dt, total, max_levels, False, time.perf_counter() - t0, hist)
+
+
+def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8,
+                 stall_window: int = 20, check_below: float = 10.0, check_every: int = 10, callback=None,
+                 **kw) -> SolveResult:
+    """Float32 iterations until converged, then float64 only if needed.
+
+    Float32 arithmetic puts a floor under the R^H it measures (the transforms'
+    rounding, not the stored states: a float32 block evaluated in float64 shows
+    a far smaller residual).  So once the float32 max R^H is below
+    ``check_below * gamma``, every ``check_every`` iterations the block is
+    converted to float64 and orthonormalised, Rayleigh-Ritz rotated and
+    measured with the float64 plan; the solve ends there when that R^H is below
+    gamma.  If float32 stalls first, float64 iterations continue from the
+    converted states at the same dt until gamma.  The two plans must describe
+    the same system; iterations and seconds of both stages are summed, and the
+    result's ``psi`` is the float64 block.
+    """
+    t0 = time.perf_counter()
+    n_check = kw.get("n_check") or plan32.n_states
+    box = {}
+
+    def accept(out, it):
+        if it % check_every or float(np.max(out["rh"][:n_check])) >= check_below * gamma:
+            return None
+        psi64 = psi32.to(torch.float64)
+        plan64.orthonormalize(psi64)
+        eig = plan64.rayleigh_ritz(psi64)
+        rh = plan64.residuals(psi64, eig)
+        box["checks"] = box.get("checks", 0) + 1
+        if float(np.max(rh[:n_check])) < gamma:
+            box["psi"] = psi64
+            return {"eig": eig, "rh": rh}
+        return None
+
+    r1 = solve(plan32, psi32, dt0=dt0, gamma=gamma, stall_window=stall_window, callback=callback, accept=accept,
+               **kw)
+    stages = [{"precision": "fp32", "iterations": r1.iterations, "seconds": round(r1.seconds, 3), "dt": r1.dt,
+               "float64_checks": box.get("checks", 0), "max_rh": float(np.max(r1.rh[:n_check]))}]
+    if r1.converged:
+        r1.stages = stages
+        r1.psi = box.get("psi")
+        return r1
+    psi64 = psi32.to(torch.float64)
+    r2 = solve(plan64, psi64, dt0=r1.dt, gamma=gamma, callback=callback, **kw)
+    stages.append({"precision": "fp64", "iterations": r2.iterations, "seconds": round(r2.seconds, 3), "dt": r2.dt,
+                   "max_rh": float(np.max(r2.rh[:n_check]))})
+    r2.iterations += r1.iterations
+    r2.levels += r1.levels - 1
+    r2.seconds = time.perf_counter() - t0
+    r2.history = r1.history + r2.history
+    r2.stages = stages
+    r2.psi = psi64
+    return r2

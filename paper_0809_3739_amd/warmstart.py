@@ -137,7 +137,14 @@ class WarmStartNet:
         self._check(self.lib.wsn_adam_step(self.h, lr, beta1, beta2, eps, self.t))
 
     def subspace_loss(self, y: torch.Tensor, target: torch.Tensor, dy: torch.Tensor | None = None):
-        """(L, ||M M^T - I||^2, dL/dy) for y, target [n, P] float32 on the device."""
+        """(L, ||M M^T - I||^2, dL/dy) for y, target [n, ...] float32 on the device."""
+        return self._loss(self.lib.wsn_subspace_loss, y, target, dy)
+
+    def procrustes_loss(self, y: torch.Tensor, target: torch.Tensor, dy: torch.Tensor | None = None):
+        """(L, sum of singular values of M, dL/dy): distance to the nearest rotation of the targets."""
+        return self._loss(self.lib.wsn_procrustes_loss, y, target, dy)
+
+    def _loss(self, fn, y, target, dy):
         n, P = int(y.shape[0]), int(np.prod(y.shape[1:]))
         _need(y, y.shape, "prediction")
         _need(target, y.shape, "target")
@@ -145,7 +152,7 @@ class WarmStartNet:
             dy = torch.empty_like(y)
         _need(dy, y.shape, "gradient")
         loss = (C.c_double * 2)()
-        self._check(self.lib.wsn_subspace_loss(self.h, _ptr(y), _ptr(target), n, P, loss, _ptr(dy)))
+        self._check(fn(self.h, _ptr(y), _ptr(target), n, P, loss, _ptr(dy)))
         return loss[0], loss[1], dy
 
 

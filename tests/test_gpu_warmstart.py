@@ -24,8 +24,9 @@ Two references for the bfloat16-MFMA convolutions:
   mask (a fraction f of the voxels) a whole term changes and the sums differ
   by about sqrt(f): a sanity bar of 0.35 for these random networks.
 
-The loss and the up-sampling run in float64 / float32 arithmetic on float32
-inputs and are held to 1e-10 (loss) and 2e-6 (gradient, up-sampling).
+The losses and the up-sampling run in float64 / float32 arithmetic on float32
+inputs and are held to 1e-10 (subspace loss), 1e-9 of ||y||^2 (Procrustes
+loss, a difference of O(n) terms) and 2e-6 (gradients, up-sampling).
 """
 import sys
 
@@ -255,6 +256,31 @@ def test_subspace_loss_matches_reference(WS, n, grid):
     L0, _, _ = net.subspace_loss(torch.from_numpy(Yr).cuda(), torch.from_numpy(T).cuda())
     Lr0, _ = unet.subspace_loss(Yr.astype(np.float64), T.astype(np.float64))
     assert abs(L0 - Lr0) <= 1e-9 * n
+
+
+@pytest.mark.parametrize("n,grid", [(24, 16), (120, 32), (5, 8), (1, 8)])
+def test_procrustes_loss_matches_reference(WS, n, grid):
+    import torch
+    say("wsn procrustes loss", n, grid)
+    P = grid ** 3
+    net = WS.WarmStartNet(grid=8, n_out=8, max_batch=1, seed=0)
+    rng = np.random.default_rng(n + 1)
+    T = np.ascontiguousarray(np.linalg.qr(rng.standard_normal((P, n)))[0].T, dtype=np.float32)
+    Y = (rng.standard_normal((n, P)) / np.sqrt(P)).astype(np.float32)
+    for case in ("random", "close"):
+        if case == "close":   # near the minimum: a rotated target plus a little noise
+            R = np.linalg.qr(rng.standard_normal((n, n)))[0]
+            Y = np.ascontiguousarray(R @ T.astype(np.float64) + 1e-3 * rng.standard_normal((n, P)) / np.sqrt(P),
+                                     dtype=np.float32)
+        L, nuc, dy = net.procrustes_loss(torch.from_numpy(Y).cuda(), torch.from_numpy(T).cuda())
+        Lr, dyr, nucr = unet.procrustes_loss(Y.astype(np.float64), T.astype(np.float64))
+        say(case, "loss", L, Lr, "nuclear", nuc, nucr)
+        # float64 throughout on float32 inputs: the loss to 1e-9 of ||y||^2 (a difference of O(n) terms)
+        assert abs(L - Lr) <= 1e-9 * max(float(np.sum(Y.astype(np.float64) ** 2)), 1.0)
+        assert abs(nuc - nucr) <= 1e-10 * nucr
+        d = dy.cpu().numpy()
+        # the float32 rotation sums n terms of size ~|y| (C rounded to float32): ~sqrt(n) eps32 |y|
+        assert np.max(np.abs(d - dyr)) <= 2e-6 * np.max(np.abs(dyr)) + 2e-6 * np.max(np.abs(Y))
 
 
 @pytest.mark.parametrize("C,d,f", [(3, 8, 2), (2, 6, 3), (120, 32, 4)])
