@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--dt", type=float, default=0.5)
     ap.add_argument("--states-per-launch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default plane-pass shapes instead of timing the candidates first")
     ap.add_argument("--solve", action="store_true",
                     help="also time a full solve to max R^H <= 1e-8 from a random start (float32 iterations, "
                          "float64 once float32 stalls)")
@@ -118,6 +120,9 @@ def main():
             torch.neg(src, out=dst)     # one read and one write of the buffer
         torch.cuda.synchronize()
         del src, dst
+    tuned = None
+    if not args.no_autotune:
+        tuned = plan.autotune(psi, args.dt, reps=2)     # outside the timed region; psi is read only
     for _ in range(args.warmup):
         plan.iterate(psi, args.dt)
     torch.cuda.synchronize()
@@ -173,6 +178,8 @@ def main():
                      "algorithmic_bytes_per_launch": prop_bytes_per_launch(dom, s.grid, m, K, fsz),
                      "traffic_bytes_per_launch": traffic_bytes,
                      "avg_launch_ms": round(avg_ms, 4)},
+        "launch_shapes": plan.plane_shape(),
+        "autotune_ms_per_step": None if tuned is None else tuned["ms_per_step"],
         "last_iteration": {"eig0": float(out["eig"][0]), "eig119": float(out["eig"][119]),
                            "max_rh": float(np.max(out["rh"][:n_states]))},
     }

@@ -157,6 +157,33 @@ mpe_status mpe_small_dense_phases(mpe_plan p, double* us);
 /* Launch-shape knob: states per propagation launch (0 = all m). */
 mpe_status mpe_set_states_per_launch(mpe_plan p, int32_t states);
 
+/* Launch shape of the forward (kernel_class MPE_KC_PLANE_FWD) or link
+ * (MPE_KC_PLANE_LINK) plane passes, for grids with nx >= 64 (smaller grids
+ * always use mode 0):
+ *   mode 0: one work-group per (z, state) plane (the default);
+ *   mode 1: blocks_per_cu work-groups per CU loop over the planes, each
+ *           loading the next plane's input while it transforms the current
+ *           one, compiled with the register budget of one work-group per CU;
+ *   mode 2: the same loop at the register budget of mode 0.
+ * Results are bitwise identical for every shape.  MPE_ERR_INVALID_ARGUMENT
+ * for another class, a mode outside 0..2 or blocks_per_cu outside 1..16
+ * (persistent modes). */
+mpe_status mpe_set_plane_shape(mpe_plan p, int32_t kernel_class, int32_t mode, int32_t blocks_per_cu);
+
+/* Current shapes: shape[4] = {fwd mode, fwd blocks_per_cu, link mode, link blocks_per_cu}. */
+mpe_status mpe_get_plane_shape(mpe_plan p, int32_t* shape);
+
+/* Autotuner: times the candidate plane shapes (mode, blocks per CU) in
+ * {(0,0), (1,1), (2,1), (2,2), (2,4)} on `reps` steps of psi (read only; the
+ * steps write the plan's workspace) at dt, and keeps the fastest shape per
+ * pass.  With cache_path (may be NULL), a line "key|fwd_mode fwd_bpc
+ * link_mode link_bpc" keyed by device, CU count, grid, precision, block size
+ * and order is looked up first (no timing on a hit) and appended after
+ * tuning.  ms_out (may be NULL) receives the chosen shapes' milliseconds per
+ * step for the forward and link passes (-1 on a cache hit).  Synchronises. */
+mpe_status mpe_autotune(mpe_plan p, const void* psi, double dt, int32_t reps, const char* cache_path,
+                        double* ms_out);
+
 /* Per-kernel timing.  When enabled, every launch is bracketed by HIP events
  * on the plan's stream; mpe_get_kernel_times synchronises and returns, per
  * kernel class (MPE_KC_*), the accumulated milliseconds and launch counts

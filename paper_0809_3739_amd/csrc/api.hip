@@ -157,6 +157,12 @@ struct mpe_plan_s {
   double tab_dt = -1.0;
   double last_dt = -1.0;
   int states_per_launch = 0;
+  // launch shapes of the forward [0] and link [1] plane passes (PlaneArgs::persist_mode,
+  // work-groups per CU); shape_ver counts changes so a captured graph can notice them
+  int pmode[2] = {0, 0};
+  int pbpc[2] = {0, 0};
+  int shape_ver = 0;
+  int n_cu = 0;
   int max_sweeps = 60;
   double jacobi_tol = 1e-13;
   double pivot_tol = 1e-13;
@@ -169,6 +175,7 @@ struct mpe_plan_s {
   hipGraphExec_t gexec = nullptr;
   const void* g_psi = nullptr;       // the graph bakes in this state block ...
   int g_spl = -1;                    // ... and this launch grouping
+  int g_shape = -1;                  // ... and these plane-pass shapes
   hipEvent_t ev_in = nullptr;
   int64_t graph_launches = 0;
 
@@ -332,6 +339,8 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
              a.fac_index = half;
              a.spec = Wk;
              a.state0 = s0;
+             a.persist_mode = p->pmode[0];
+             a.persist_blocks = p->pbpc[0] * p->n_cu;
              return launch_plane(p->dbl, PM_FWD, p->nx, a, p->nz, cnt, p->st);
            }));
     toc(p, t);
@@ -351,6 +360,8 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
                  a.fac = p->fac;
                  a.fac_index = full;
                  a.state0 = s0;
+                 a.persist_mode = p->pmode[1];
+                 a.persist_blocks = p->pbpc[1] * p->n_cu;
                  return launch_plane(p->dbl, PM_LINK, p->nx, a, p->nz, cnt, p->st);
                }));
         toc(p, t);
@@ -584,6 +595,7 @@ void drop_graph(mpe_plan p) {
   p->graph = nullptr;
   p->g_psi = nullptr;
   p->g_spl = -1;
+  p->g_shape = -1;
 }
 
 // Capture enqueue_iterate(psi) on the private stream into an executable graph.
@@ -607,6 +619,7 @@ mpe_status capture_iterate(mpe_plan p, void* psi) {
   HIPCHK(p, hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
   p->g_psi = psi;
   p->g_spl = p->states_per_launch;
+  p->g_shape = p->shape_ver;
   return MPE_OK;
 }
 
@@ -752,6 +765,14 @@ mpe_status mpe_plan_create(mpe_plan* out, const int32_t grid[3], const double bo
     return MPE_ERR_OUT_OF_MEMORY;
   }
   p->status = reinterpret_cast<int*>(p->res + 6 * MAXM);
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || p->n_cu < 1) {
+      mpe_plan_destroy(p);
+      return MPE_ERR_DEVICE;
+    }
+  }
   if (prepare_small_dense() != hipSuccess) {
     mpe_plan_destroy(p);
     return MPE_ERR_DEVICE;
@@ -908,7 +929,7 @@ mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh
   if (s != MPE_OK) return s;
   p->last_dt = dt;
   if (p->use_graph && !p->prof) {
-    if (!p->gexec || p->g_psi != psi || p->g_spl != p->states_per_launch) {
+    if (!p->gexec || p->g_psi != psi || p->g_spl != p->states_per_launch || p->g_shape != p->shape_ver) {
       s = capture_iterate(p, psi);
       if (s != MPE_OK) return s;
     }
@@ -952,6 +973,124 @@ mpe_status mpe_set_states_per_launch(mpe_plan p, int32_t states) {
   if (!p) return MPE_ERR_INVALID_ARGUMENT;
   if (states < 0) return fail(p, MPE_ERR_INVALID_ARGUMENT, "states must be >= 0");
   p->states_per_launch = states;
+  return MPE_OK;
+}
+
+mpe_status mpe_set_plane_shape(mpe_plan p, int32_t kernel_class, int32_t mode, int32_t blocks_per_cu) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  const int c = kernel_class == MPE_KC_PLANE_FWD ? 0 : kernel_class == MPE_KC_PLANE_LINK ? 1 : -1;
+  if (c < 0) return fail(p, MPE_ERR_INVALID_ARGUMENT, "kernel_class must be MPE_KC_PLANE_FWD or MPE_KC_PLANE_LINK");
+  if (mode < 0 || mode > 2) return fail(p, MPE_ERR_INVALID_ARGUMENT, "mode must be 0, 1 or 2");
+  if (mode > 0 && (blocks_per_cu < 1 || blocks_per_cu > 16))
+    return fail(p, MPE_ERR_INVALID_ARGUMENT, "blocks_per_cu must be in [1, 16] for a persistent shape");
+  p->pmode[c] = mode;
+  p->pbpc[c] = mode > 0 ? blocks_per_cu : 0;
+  p->shape_ver++;
+  return MPE_OK;
+}
+
+mpe_status mpe_get_plane_shape(mpe_plan p, int32_t* shape) {
+  if (!p || !shape) return MPE_ERR_INVALID_ARGUMENT;
+  shape[0] = p->pmode[0];
+  shape[1] = p->pbpc[0];
+  shape[2] = p->pmode[1];
+  shape[3] = p->pbpc[1];
+  return MPE_OK;
+}
+
+mpe_status mpe_autotune(mpe_plan p, const void* psi, double dt, int32_t reps, const char* cache_path,
+                        double* ms_out) {
+  if (!p || !psi) return MPE_ERR_INVALID_ARGUMENT;
+  if (!(dt > 0.0) || !std::isfinite(dt) || reps < 1) return fail(p, MPE_ERR_INVALID_ARGUMENT, "dt > 0, reps >= 1");
+  if (!p->have_v) return fail(p, MPE_ERR_STATE, "no potential set (mpe_set_potential)");
+  // cache key: device, grid, precision, block size, order
+  std::string key;
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+      return fail(p, MPE_ERR_DEVICE, "device query failed");
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s/%d %d %d %d %s m%d K%d", prop.gcnArchName, p->n_cu, p->nx, p->ny, p->nz,
+                  p->dbl ? "fp64" : "fp32", p->m, p->K);
+    key = buf;
+    for (char& ch : key)
+      if (ch == '\n' || ch == '|') ch = ' ';
+  }
+  if (cache_path && *cache_path) {
+    std::FILE* f = std::fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      int best[4];
+      bool hit = false;
+      while (std::fgets(line, sizeof line, f)) {
+        char* bar = std::strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        if (key == line && std::sscanf(bar + 1, "%d %d %d %d", &best[0], &best[1], &best[2], &best[3]) == 4)
+          hit = true;   // the last matching line wins
+      }
+      std::fclose(f);
+      if (hit) {
+        mpe_status s = mpe_set_plane_shape(p, MPE_KC_PLANE_FWD, best[0], best[1]);
+        if (s == MPE_OK) s = mpe_set_plane_shape(p, MPE_KC_PLANE_LINK, best[2], best[3]);
+        if (s == MPE_OK) {
+          if (ms_out) ms_out[0] = ms_out[1] = -1.0;
+          return MPE_OK;
+        }
+      }
+    }
+  }
+  mpe_status s = ensure_tables(p, dt);
+  if (s != MPE_OK) return s;
+  // candidate shapes (mode, work-groups per CU), timed on steps psi -> phi
+  const int cand[][2] = {{0, 0}, {1, 1}, {2, 1}, {2, 2}, {2, 4}};
+  const int nc = (int)(sizeof cand / sizeof cand[0]);
+  double best_ms[2] = {1e300, 1e300};
+  int best_c[2] = {0, 0};
+  const bool prof0 = p->prof;
+  collect_times(p);
+  double saved_ms[MPE_KC_COUNT];
+  int64_t saved_n[MPE_KC_COUNT];
+  for (int i = 0; i < MPE_KC_COUNT; ++i) saved_ms[i] = p->kms[i], saved_n[i] = p->kcount[i];
+  p->prof = true;
+  for (int c = 0; c < nc; ++c) {
+    p->pmode[0] = p->pmode[1] = cand[c][0];
+    p->pbpc[0] = p->pbpc[1] = cand[c][1];
+    s = enqueue_step(p, psi, p->phi);   // warm-up
+    if (s != MPE_OK) break;
+    collect_times(p);
+    for (int i = 0; i < MPE_KC_COUNT; ++i) p->kms[i] = 0, p->kcount[i] = 0;
+    for (int r = 0; r < reps && s == MPE_OK; ++r) s = enqueue_step(p, psi, p->phi);
+    if (s != MPE_OK) break;
+    collect_times(p);
+    const double t[2] = {p->kms[MPE_KC_PLANE_FWD], p->kms[MPE_KC_PLANE_LINK]};
+    for (int k = 0; k < 2; ++k)
+      if (t[k] < best_ms[k]) best_ms[k] = t[k], best_c[k] = c;
+  }
+  for (int i = 0; i < MPE_KC_COUNT; ++i) p->kms[i] = saved_ms[i], p->kcount[i] = saved_n[i];
+  p->prof = prof0;
+  if (s != MPE_OK) {
+    p->pmode[0] = p->pmode[1] = p->pbpc[0] = p->pbpc[1] = 0;
+    p->shape_ver++;
+    return s;
+  }
+  p->pmode[0] = cand[best_c[0]][0];
+  p->pbpc[0] = cand[best_c[0]][1];
+  p->pmode[1] = cand[best_c[1]][0];
+  p->pbpc[1] = cand[best_c[1]][1];
+  p->shape_ver++;
+  if (ms_out) {
+    ms_out[0] = best_ms[0] / reps;
+    ms_out[1] = best_ms[1] / reps;
+  }
+  if (cache_path && *cache_path) {
+    std::FILE* f = std::fopen(cache_path, "a");
+    if (f) {
+      std::fprintf(f, "%s|%d %d %d %d\n", key.c_str(), p->pmode[0], p->pbpc[0], p->pmode[1], p->pbpc[1]);
+      std::fclose(f);
+    }
+  }
   return MPE_OK;
 }
 

@@ -20,6 +20,25 @@ struct alignas(2 * sizeof(F)) cx {
   F x, y;
 };
 
+// Pointer into the global address space (global_* rather than flat_* memory
+// instructions when the address space cannot be inferred).
+template <typename T>
+using gp = T __attribute__((address_space(1)))*;
+
+// Complex loads and stores through global pointers, as one 2-element vector
+// access (dwordx2 / dwordx4).
+template <typename F>
+using vec2 = F __attribute__((ext_vector_type(2)));
+template <typename F>
+__device__ __forceinline__ cx<F> gload(gp<const cx<F>> p) {
+  const vec2<F> t = *reinterpret_cast<gp<const vec2<F>>>(p);
+  return cx<F>{t.x, t.y};
+}
+template <typename F>
+__device__ __forceinline__ void gstore(gp<cx<F>> p, cx<F> v) {
+  *reinterpret_cast<gp<vec2<F>>>(p) = vec2<F>{v.x, v.y};
+}
+
 template <typename F>
 __device__ __forceinline__ cx<F> mk(F a, F b) { return cx<F>{a, b}; }
 template <typename F>

@@ -67,15 +67,17 @@ struct PlaneOcc {
   static constexpr int value = W < 1 ? 1 : (W > WMAX ? WMAX : W);
 };
 
-template <typename F, int NX, int MODE>
+// PERSIST: 0 = one plane per work-group; 1 = persistent, register budget of one
+// work-group per CU; 2 = persistent at the occupancy of PERSIST = 0.
+template <typename F, int NX, int MODE, int PERSIST>
 struct PlaneWaves {
   static constexpr int one_wg = (PlaneShape<NX>::BLOCK / 64 + 3) / 4;
-  static constexpr int value = MODE == PM_TAIL ? one_wg : PlaneOcc<F, NX>::value;
+  static constexpr int value = (MODE == PM_TAIL || PERSIST == 1) ? one_wg : PlaneOcc<F, NX>::value;
 };
 
-template <typename F, int NX, int MODE>
-__global__ __launch_bounds__(PlaneShape<NX>::BLOCK) __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE>::value)))
-void plane_kernel(PlaneArgs a) {
+template <typename F, int NX, int MODE, int PERSIST>
+__global__ __launch_bounds__(PlaneShape<NX>::BLOCK)
+__attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) void plane_kernel(PlaneArgs a) {
   constexpr int NY = NX;
   constexpr int BLOCK = PlaneShape<NX>::BLOCK;
   constexpr int LX = NX / 2, NXH = LX + 1, HALF = LX / 2;
@@ -91,6 +93,7 @@ void plane_kernel(PlaneArgs a) {
   constexpr bool ROWWAVE = (64 % TX == 0);
   static_assert(NCF * TY <= BLOCK, "one column round");
   static_assert(NCF % 2 == 0, "column pairs");
+  static_assert(PERSIST == 0 || MODE == PM_FWD || MODE == PM_LINK, "persistent launches: forward and link passes");
   constexpr bool TAIL_PREFETCH = sizeof(F) == 4 && EY <= 16;
 
   __shared__ cx<F> lds[NY * SROW];
@@ -98,35 +101,40 @@ void plane_kernel(PlaneArgs a) {
   __shared__ cx<F> tw_x[LX], tw_y[NY], tw_w[HALF + 1];
 
   const int tid = threadIdx.x;
-  const int z = blockIdx.x;
-  const long s = (long)blockIdx.y + a.state0;
   const long plane_real = (long)NY * NX;
   const long plane_spec = (long)NY * NXH;
-  const long z_real = (long)z * plane_real;
-  const long z_spec = (long)z * plane_spec;
-  // this state's arrays (plane z offsets added below)
-  const F* rin;
-  F* rout;
-  cx<F>* spec;
-  long chain_stride;
-  const F* facb;
-  if (a.desc) {
-    const StateDesc& d = a.desc[s];
-    rin = reinterpret_cast<const F*>(d.real_in);
-    rout = reinterpret_cast<F*>(d.real_out);
-    chain_stride = d.chain_stride;
-    spec = reinterpret_cast<cx<F>*>(d.spec) + (long)a.chain * chain_stride;
-    facb = reinterpret_cast<const F*>(MODE == PM_HTAIL ? d.V : d.fac);
-  } else {
-    rin = reinterpret_cast<const F*>(a.real_in) + s * a.real_state_stride;
-    rout = reinterpret_cast<F*>(a.real_out) + s * a.real_state_stride;
-    spec = reinterpret_cast<cx<F>*>(a.spec) + s * a.spec_state_stride;
-    chain_stride = a.chain_stride;
-    facb = reinterpret_cast<const F*>(a.fac);
-  }
-  const F* facz = (MODE == PM_HTAIL || MODE == PM_TAIL || a.fac_index < 0 || !facb)
-                      ? facb
-                      : facb + (long)a.fac_index * a.fac_table_stride;
+  // the arrays of state s (plane offsets added by the passes)
+  // (explicitly global pointers: the loads and stores stay global_* instructions
+  // after the pointers pass through this struct and the lambdas below)
+  struct Ptrs {
+    gp<const F> rin;
+    gp<F> rout;
+    gp<cx<F>> spec;
+    long chain_stride;
+    gp<const F> facb;
+    gp<const F> facz;
+  };
+  auto ptrs_of = [&](long s) {
+    Ptrs P;
+    if (a.desc) {
+      const StateDesc& d = a.desc[s];
+      P.rin = (gp<const F>)reinterpret_cast<const F*>(d.real_in);
+      P.rout = (gp<F>)reinterpret_cast<F*>(d.real_out);
+      P.chain_stride = d.chain_stride;
+      P.spec = (gp<cx<F>>)reinterpret_cast<cx<F>*>(d.spec) + (long)a.chain * P.chain_stride;
+      P.facb = (gp<const F>)reinterpret_cast<const F*>(MODE == PM_HTAIL ? d.V : d.fac);
+    } else {
+      P.rin = (gp<const F>)reinterpret_cast<const F*>(a.real_in) + s * a.real_state_stride;
+      P.rout = (gp<F>)reinterpret_cast<F*>(a.real_out) + s * a.real_state_stride;
+      P.spec = (gp<cx<F>>)reinterpret_cast<cx<F>*>(a.spec) + s * a.spec_state_stride;
+      P.chain_stride = a.chain_stride;
+      P.facb = (gp<const F>)reinterpret_cast<const F*>(a.fac);
+    }
+    P.facz = (MODE == PM_HTAIL || MODE == PM_TAIL || a.fac_index < 0 || !P.facb)
+                 ? P.facb
+                 : P.facb + (long)a.fac_index * a.fac_table_stride;
+    return P;
+  };
 
   {
     const cx<F>* gx = reinterpret_cast<const cx<F>*>(a.rx);
@@ -151,6 +159,12 @@ void plane_kernel(PlaneArgs a) {
   const int col = (g == 0) ? (h ? HALF : 0) : (h ? LX - g : g);   // LDS / spectrum column
   const int tyc = cact ? ty : 0;
   auto cbuf = [&](int i) { return &lds[i * SROW + col]; };
+  // Row-transform exchange slots: element i of row r at r * SROW + i + i / EX.
+  // The exchange writes lane t's outputs at E t + k; one pad slot per E
+  // elements moves the T lanes of a row to different LDS banks (without it
+  // they share a bank), and the strided reads t + T m stay conflict-free.
+  static_assert((LX - 1) + (LX - 1) / EX < SROW, "padded row exchange fits the row stride");
+  auto rowbuf = [&](int r) { return [&, r](int i) { return &lds[r * SROW + i + i / EX]; }; };
 
   // W^k for k = 0..LX (W^(LX-j) = -conj W^j)
   auto wk = [&](int k) -> cx<F> {
@@ -159,17 +173,16 @@ void plane_kernel(PlaneArgs a) {
 
   // ---- spectrum in: column loads (issued early when pipelined), inverse y FFT,
   //      c2r split in registers, Z rows to LDS
-  auto column_load = [&](const cx<F>* __restrict__ spec, cx<F>* v) {
+  // The packed lane (DC and Nyquist columns) loads like every other lane plus
+  // the row's Nyquist value, which all lanes load too (one address per row), so
+  // the loads stay full-wave instructions without a divergent branch.
+  auto column_load = [&](gp<const cx<F>> __restrict__ spec, cx<F>* v) {
     if (cact) {
 #pragma unroll
       for (int m = 0; m < EY; ++m) {
         const long o = (long)(tyc + TY * m) * NXH;
-        if (packed) {
-          const cx<F> y0 = spec[o], yl = spec[o + LX];
-          v[m] = cx<F>{y0.x - yl.y, y0.y + yl.x};            // Y0 + i Y_LX
-        } else {
-          v[m] = spec[o + col];
-        }
+        const cx<F> y0 = gload<F>(spec + o + col), yl = gload<F>(spec + o + LX);
+        v[m] = packed ? cx<F>{y0.x - yl.y, y0.y + yl.x} : y0;   // Y0 + i Y_LX
       }
     }
   };
@@ -199,14 +212,14 @@ void plane_kernel(PlaneArgs a) {
     }
     __syncthreads();
   };
-  auto column_inverse = [&](const cx<F>* __restrict__ spec) {
+  auto column_inverse = [&](gp<const cx<F>> __restrict__ spec) {
     cx<F> v[EY];
     column_load(spec, v);
     column_inverse_regs(v);
   };
 
   // ---- columns forward out: r2c split on load, forward y FFT, store
-  auto column_forward_store = [&](cx<F>* __restrict__ spec) {
+  auto column_forward_store = [&](gp<cx<F>> __restrict__ spec) {
     __syncthreads();
     cx<F> v[EY];
     if (cact) {
@@ -227,89 +240,161 @@ void plane_kernel(PlaneArgs a) {
     }
     __syncthreads();   // every Z value read before the exchanges reuse the columns
     fft<NY, -1>(v, tyc, cact, cbuf, ry);
-    if (cact && !packed) {
-#pragma unroll
-      for (int m = 0; m < EY; ++m) spec[(long)(tyc + TY * m) * NXH + col] = v[m];
-    }
-    // unpack the DC / Nyquist column: X0[k] = (C[k] + conj C[-k])/2, X_LX[k] = -i (C[k] - conj C[-k])/2
+    // unpack the DC / Nyquist column: X0[k] = (C[k] + conj C[-k])/2, X_LX[k] = -i (C[k] - conj C[-k])/2;
+    // C[-k] comes from another wave through LDS, then one store per row serves every lane
     if (cact && packed) {
 #pragma unroll
       for (int m = 0; m < EY; ++m) lds[(tyc + TY * m) * SROW] = v[m];
     }
     __syncthreads();
-    if (cact && packed) {
+    if (cact) {
 #pragma unroll
       for (int m = 0; m < EY; ++m) {
         const int ky = tyc + TY * m;
         const cx<F> c = v[m], cm = conj(lds[((NY - ky) % NY) * SROW]);
-        spec[(long)ky * NXH] = scale(c + cm, F(0.5));
-        spec[(long)ky * NXH + LX] = muli<-1>(scale(c - cm, F(0.5)));
+        const F hx = F(0.5) * (c.x + cm.x), hy = F(0.5) * (c.y + cm.y);
+        cx<F> o;
+        o.x = packed ? hx : c.x;
+        o.y = packed ? hy : c.y;
+        gstore<F>(spec + (long)ky * NXH + col, o);
+      }
+      if (packed) {
+#pragma unroll
+        for (int m = 0; m < EY; ++m) {
+          const int ky = tyc + TY * m;
+          const cx<F> c = v[m], cm = conj(lds[((NY - ky) % NY) * SROW]);
+          gstore<F>(spec + (long)ky * NXH + LX, muli<-1>(scale(c - cm, F(0.5))));
+        }
       }
     }
   };
 
-  if constexpr (MODE == PM_FWD) {
-    const F* __restrict__ src = rin + z_real;
-    const F* __restrict__ fac = (a.fac_index >= 0 && facz) ? facz + z_real : nullptr;
+  if constexpr (MODE == PM_FWD || MODE == PM_LINK) {
+    // Planes of this work-group: one (z, state) pair, or with PERSIST every
+    // gridDim.x-th plane of the launch; the next plane's input (rows for the
+    // forward pass, spectrum columns for the link pass) is loaded while the
+    // current plane is transformed.
+    const long nplanes = PERSIST ? (long)a.nz * a.nstates : 1;
+    long p = PERSIST ? (long)blockIdx.x : 0;
+    // (a persistent launch has at most nplanes work-groups: p < nplanes here)
+    auto locate = [&](long q, int& zq, Ptrs& Pq) {
+      long sq;
+      if constexpr (PERSIST != 0) {
+        zq = (int)(q % a.nz);
+        sq = q / a.nz + a.state0;
+      } else {
+        zq = blockIdx.x;
+        sq = (long)blockIdx.y + a.state0;
+      }
+      Pq = ptrs_of(sq);
+    };
+    constexpr int NPRE = MODE == PM_FWD ? XR * EX : EY;
+    cx<F> pre[NPRE];
+    auto prefetch = [&](int zq, const Ptrs& Pq) {
+      if constexpr (MODE == PM_FWD) {
+        gp<const F> __restrict__ src = Pq.rin + (long)zq * plane_real;
 #pragma unroll
-    for (int rr = 0; rr < XR; ++rr) {
-      const int row = rr * RPR + rloc;
-      const bool act = row < NY;
-      const int rowc = act ? row : 0;
-      cx<F> v[EX];
-      if (act) {
-        const cx<F>* s2 = reinterpret_cast<const cx<F>*>(src + (long)row * NX);
+        for (int rr = 0; rr < XR; ++rr) {
+          const int row = rr * RPR + rloc;
+          if (row < NY) {
+            gp<const cx<F>> s2 = reinterpret_cast<gp<const cx<F>>>(src + (long)row * NX);
 #pragma unroll
-        for (int m = 0; m < EX; ++m) v[m] = s2[tx + TX * m];
-        if (fac) {
-          const cx<F>* f2 = reinterpret_cast<const cx<F>*>(fac + (long)row * NX);
+            for (int m = 0; m < EX; ++m) pre[rr * EX + m] = gload<F>(s2 + tx + TX * m);
+          }
+        }
+      } else {
+        column_load(Pq.spec + (long)zq * plane_spec, pre);
+      }
+    };
+    int z;
+    Ptrs P;
+    locate(p, z, P);
+    prefetch(z, P);
+    for (;;) {
+      const long pn = p + (PERSIST ? (long)gridDim.x : 0);
+      const bool more = PERSIST && pn < nplanes;
+      int zn = z;
+      Ptrs Pn = P;
+      const long z_real = (long)z * plane_real;
+      if constexpr (MODE == PM_FWD) {
+        gp<const F> __restrict__ fac = (a.fac_index >= 0 && P.facz) ? P.facz + z_real : nullptr;
 #pragma unroll
-          for (int m = 0; m < EX; ++m) {
-            const cx<F> fv = f2[tx + TX * m];
-            v[m].x *= fv.x;
-            v[m].y *= fv.y;
+        for (int rr = 0; rr < XR; ++rr) {
+          const int row = rr * RPR + rloc;
+          const bool act = row < NY;
+          const int rowc = act ? row : 0;
+          cx<F> v[EX];
+#pragma unroll
+          for (int m = 0; m < EX; ++m) v[m] = pre[rr * EX + m];
+          if (act && fac) {
+            gp<const cx<F>> f2 = reinterpret_cast<gp<const cx<F>>>(fac + (long)row * NX);
+#pragma unroll
+            for (int m = 0; m < EX; ++m) {
+              const cx<F> fv = gload<F>(f2 + tx + TX * m);
+              v[m].x *= fv.x;
+              v[m].y *= fv.y;
+            }
+          }
+          fft<LX, -1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
+          if (act) {
+#pragma unroll
+            for (int m = 0; m < EX; ++m) lds[row * SROW + tx + TX * m] = v[m];
+          }
+        }
+        if (more) {
+          locate(pn, zn, Pn);
+          prefetch(zn, Pn);
+        }
+      } else {
+        column_inverse_regs(pre);
+        if (more) {
+          locate(pn, zn, Pn);
+          prefetch(zn, Pn);
+        }
+        gp<const F> __restrict__ fac = P.facz + z_real;
+#pragma unroll
+        for (int rr = 0; rr < XR; ++rr) {
+          const int row = rr * RPR + rloc;
+          const bool act = row < NY;
+          const int rowc = act ? row : 0;
+          cx<F> v[EX];
+          if (act) {
+#pragma unroll
+            for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + tx + TX * m];
+          }
+          fft<LX, +1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
+          if (act) {
+            gp<const cx<F>> f2 = reinterpret_cast<gp<const cx<F>>>(fac + (long)row * NX);
+#pragma unroll
+            for (int m = 0; m < EX; ++m) {
+              const cx<F> fv = gload<F>(f2 + tx + TX * m);
+              v[m].x *= fv.x;
+              v[m].y *= fv.y;
+            }
+          }
+          fft<LX, -1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
+          if (act) {
+#pragma unroll
+            for (int m = 0; m < EX; ++m) lds[row * SROW + tx + TX * m] = v[m];
           }
         }
       }
-      fft<LX, -1, ROWWAVE>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
-      if (act) {
-#pragma unroll
-        for (int m = 0; m < EX; ++m) lds[row * SROW + tx + TX * m] = v[m];
-      }
+      column_forward_store(P.spec + (long)z * plane_spec);
+      if (!more) break;
+      __syncthreads();   // the DC / Nyquist epilogue still reads the plane in LDS
+      p = pn;
+      z = zn;
+      P = Pn;
     }
-    column_forward_store(spec + z_spec);
-  } else if constexpr (MODE == PM_LINK) {
-    column_inverse(spec + z_spec);
-    const F* __restrict__ fac = facz + z_real;
-#pragma unroll
-    for (int rr = 0; rr < XR; ++rr) {
-      const int row = rr * RPR + rloc;
-      const bool act = row < NY;
-      const int rowc = act ? row : 0;
-      cx<F> v[EX];
-      cx<F> fv[EX];
-      if (act) {
-        const cx<F>* f2 = reinterpret_cast<const cx<F>*>(fac + (long)row * NX);
-#pragma unroll
-        for (int m = 0; m < EX; ++m) {
-          v[m] = lds[row * SROW + tx + TX * m];
-          fv[m] = f2[tx + TX * m];
-        }
-      }
-      fft<LX, +1, ROWWAVE>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
-#pragma unroll
-      for (int m = 0; m < EX; ++m) {
-        v[m].x *= fv[m].x;
-        v[m].y *= fv[m].y;
-      }
-      fft<LX, -1, ROWWAVE>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
-      if (act) {
-#pragma unroll
-        for (int m = 0; m < EX; ++m) lds[row * SROW + tx + TX * m] = v[m];
-      }
-    }
-    column_forward_store(spec + z_spec);
   } else if constexpr (MODE == PM_TAIL) {
+    const int z = blockIdx.x;
+    const Ptrs P = ptrs_of((long)blockIdx.y + a.state0);
+    const long z_real = (long)z * plane_real, z_spec = (long)z * plane_spec;
+    gp<cx<F>> spec = P.spec;
+    gp<const F> facb = P.facb;
+    const long chain_stride = P.chain_stride;
+    gp<const F> rin = P.rin;
+    gp<F> rout = P.rout;
     double acc[XR][EX][2];
 #pragma unroll
     for (int rr = 0; rr < XR; ++rr)
@@ -317,11 +402,11 @@ void plane_kernel(PlaneArgs a) {
       for (int m = 0; m < EX; ++m) acc[rr][m][0] = acc[rr][m][1] = 0.0;
     // the next chain's column loads are issued before this chain's row work,
     // so their latency hides behind it (one work-group per CU here)
-    const cx<F>* spec0 = spec + z_spec;
+    gp<const cx<F>> spec0 = spec + z_spec;
     cx<F> vc[EY];
     column_load(spec0, vc);
     for (int k = 0; k < a.K; ++k) {
-      const F* __restrict__ fac = facb + (long)(2 * k + 1) * a.fac_table_stride + z_real;
+      gp<const F> __restrict__ fac = facb + (long)(2 * k + 1) * a.fac_table_stride + z_real;
       const double ck = a.coef[k];
       column_inverse_regs(vc);
       // (float64 planes, and float32 planes with 24-element columns, have no
@@ -341,12 +426,12 @@ void plane_kernel(PlaneArgs a) {
 #pragma unroll
           for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + tx + TX * m];
         }
-        fft<LX, +1, ROWWAVE>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
+        fft<LX, +1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
         if (act) {
-          const cx<F>* f2 = reinterpret_cast<const cx<F>*>(fac + (long)row * NX);
+          gp<const cx<F>> f2 = reinterpret_cast<gp<const cx<F>>>(fac + (long)row * NX);
 #pragma unroll
           for (int m = 0; m < EX; ++m) {
-            const cx<F> fv = f2[tx + TX * m];
+            const cx<F> fv = gload<F>(f2 + tx + TX * m);
             acc[rr][m][0] += ck * (double)(v[m].x * fv.x);
             acc[rr][m][1] += ck * (double)(v[m].y * fv.y);
           }
@@ -357,21 +442,29 @@ void plane_kernel(PlaneArgs a) {
         if (k + 1 < a.K) column_load(spec0 + (long)(k + 1) * chain_stride, vc);
       }
     }
-    F* __restrict__ dst = rout + z_real;
+    gp<F> __restrict__ dst = rout + z_real;
 #pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
       if (row < NY) {
-        cx<F>* d2 = reinterpret_cast<cx<F>*>(dst + (long)row * NX);
+        gp<cx<F>> d2 = reinterpret_cast<gp<cx<F>>>(dst + (long)row * NX);
 #pragma unroll
-        for (int m = 0; m < EX; ++m) d2[tx + TX * m] = cx<F>{(F)acc[rr][m][0], (F)acc[rr][m][1]};
+        for (int m = 0; m < EX; ++m) gstore<F>(d2 + tx + TX * m, cx<F>{(F)acc[rr][m][0], (F)acc[rr][m][1]});
       }
     }
   } else {  // PM_HTAIL
+    const int z = blockIdx.x;
+    const Ptrs P = ptrs_of((long)blockIdx.y + a.state0);
+    const long z_real = (long)z * plane_real, z_spec = (long)z * plane_spec;
+    gp<cx<F>> spec = P.spec;
+    gp<const F> facb = P.facb;
+    const long chain_stride = P.chain_stride;
+    gp<const F> rin = P.rin;
+    gp<F> rout = P.rout;
     column_inverse(spec + z_spec);
-    const F* __restrict__ phi = rin + z_real;
-    const F* __restrict__ V = facb + z_real;
-    F* __restrict__ dst = rout + z_real;
+    gp<const F> __restrict__ phi = rin + z_real;
+    gp<const F> __restrict__ V = facb + z_real;
+    gp<F> __restrict__ dst = rout + z_real;
 #pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
@@ -382,15 +475,15 @@ void plane_kernel(PlaneArgs a) {
 #pragma unroll
         for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + tx + TX * m];
       }
-      fft<LX, +1, ROWWAVE>(v, tx, act, [&](int i) { return &lds[rowc * SROW + i]; }, rx);
+      fft<LX, +1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
       if (act) {
-        const cx<F>* p2 = reinterpret_cast<const cx<F>*>(phi + (long)row * NX);
-        const cx<F>* v2 = reinterpret_cast<const cx<F>*>(V + (long)row * NX);
-        cx<F>* d2 = reinterpret_cast<cx<F>*>(dst + (long)row * NX);
+        gp<const cx<F>> p2 = reinterpret_cast<gp<const cx<F>>>(phi + (long)row * NX);
+        gp<const cx<F>> v2 = reinterpret_cast<gp<const cx<F>>>(V + (long)row * NX);
+        gp<cx<F>> d2 = reinterpret_cast<gp<cx<F>>>(dst + (long)row * NX);
 #pragma unroll
         for (int m = 0; m < EX; ++m) {
-          const cx<F> pv = p2[tx + TX * m], wv = v2[tx + TX * m];
-          d2[tx + TX * m] = cx<F>{v[m].x + wv.x * pv.x, v[m].y + wv.y * pv.y};
+          const cx<F> pv = gload<F>(p2 + tx + TX * m), wv = gload<F>(v2 + tx + TX * m);
+          gstore<F>(d2 + tx + TX * m, cx<F>{v[m].x + wv.x * pv.x, v[m].y + wv.y * pv.y});
         }
       }
     }
@@ -471,13 +564,30 @@ __global__ __launch_bounds__(256) void pencil_kernel(PencilArgs a) {
 // ------------------------------------------------------------------ launchers
 template <typename F, int N>
 static hipError_t launch_plane_n(int mode, const PlaneArgs& a, int nz, int nstates, hipStream_t st) {
-  dim3 grid(nz, nstates);
   dim3 block(PlaneShape<N>::BLOCK);
+  if constexpr (N >= 64) {
+    if (a.persist_blocks > 0 && (a.persist_mode == 1 || a.persist_mode == 2) && (mode == PM_FWD || mode == PM_LINK)) {
+      PlaneArgs b = a;
+      b.nz = nz;
+      b.nstates = nstates;
+      const long nplanes = (long)nz * nstates;
+      dim3 grid((unsigned)(a.persist_blocks < nplanes ? a.persist_blocks : nplanes));
+      if (a.persist_mode == 1) {
+        if (mode == PM_FWD) hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD, 1>), grid, block, 0, st, b);
+        else hipLaunchKernelGGL((plane_kernel<F, N, PM_LINK, 1>), grid, block, 0, st, b);
+      } else {
+        if (mode == PM_FWD) hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD, 2>), grid, block, 0, st, b);
+        else hipLaunchKernelGGL((plane_kernel<F, N, PM_LINK, 2>), grid, block, 0, st, b);
+      }
+      return hipGetLastError();
+    }
+  }
+  dim3 grid(nz, nstates);
   switch (mode) {
-    case PM_FWD: hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD>), grid, block, 0, st, a); break;
-    case PM_LINK: hipLaunchKernelGGL((plane_kernel<F, N, PM_LINK>), grid, block, 0, st, a); break;
-    case PM_TAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_TAIL>), grid, block, 0, st, a); break;
-    case PM_HTAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_HTAIL>), grid, block, 0, st, a); break;
+    case PM_FWD: hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD, 0>), grid, block, 0, st, a); break;
+    case PM_LINK: hipLaunchKernelGGL((plane_kernel<F, N, PM_LINK, 0>), grid, block, 0, st, a); break;
+    case PM_TAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_TAIL, 0>), grid, block, 0, st, a); break;
+    case PM_HTAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_HTAIL, 0>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -43,6 +43,14 @@ struct PlaneArgs {
   int state0;                 // first state of this launch
   int K;                      // PM_TAIL: number of chains
   double coef[MAX_K];         // PM_TAIL: c_1..c_K
+  // PM_FWD / PM_LINK launch shape (grids of 64 points and more): persist_mode
+  // 0 = one work-group per (z, state) plane; 1 / 2 = persist_blocks resident
+  // work-groups looping over the planes, each loading the next plane's input
+  // while it transforms the current one, with the register budget of one
+  // work-group per CU (1) or of the one-plane launch (2)
+  int persist_mode;
+  int persist_blocks;
+  int nz, nstates;            // set by the launcher for persistent launches
 };
 
 struct PencilArgs {

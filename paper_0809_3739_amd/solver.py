@@ -138,6 +138,25 @@ class Plan:
     def set_states_per_launch(self, states: int):
         self._check(self.lib.mpe_set_states_per_launch(self.h, int(states)))
 
+    def set_plane_shape(self, kernel_class: str, mode: int, blocks_per_cu: int = 0):
+        """kernel_class "plane_fwd" or "plane_link"; see mpe_set_plane_shape."""
+        kc = _lib.KERNEL_CLASSES.index(kernel_class)
+        self._check(self.lib.mpe_set_plane_shape(self.h, kc, int(mode), int(blocks_per_cu)))
+
+    def plane_shape(self) -> dict:
+        buf = (C.c_int32 * 4)()
+        self._check(self.lib.mpe_get_plane_shape(self.h, buf))
+        return {"plane_fwd": (buf[0], buf[1]), "plane_link": (buf[2], buf[3])}
+
+    def autotune(self, psi: torch.Tensor, dt: float, reps: int = 2, cache: str | None = None) -> dict:
+        """Pick the fastest plane-pass shapes (mpe_autotune); ``cache`` defaults to $MPE_TUNE_CACHE."""
+        import os
+        cache = os.environ.get("MPE_TUNE_CACHE") if cache is None else cache
+        ms = np.zeros(2)
+        self._check(self.lib.mpe_autotune(self.h, self._arr(psi), float(dt), int(reps),
+                                          cache.encode() if cache else None, _dptr(ms)))
+        return {**self.plane_shape(), "ms_per_step": {"plane_fwd": ms[0], "plane_link": ms[1]}}
+
     def profile(self, on: bool = True):
         self._check(self.lib.mpe_profile_enable(self.h, 1 if on else 0))
 

@@ -88,7 +88,8 @@ def generate(seeds, fine: int = 64, d: int = COARSE, n_guard: int = 8, order: in
 
 
 def train(net: WarmStartNet, X: torch.Tensor, T: torch.Tensor, steps: int, batch: int = 4, lr: float = 1e-3,
-          lr_final: float = 1e-4, seed: int = 0, log=print, log_every: int = 200, loss: str = "procrustes"):
+          lr_final: float = 1e-4, seed: int = 0, log=print, log_every: int = 200, loss: str = "procrustes",
+          checkpoint=None, checkpoint_every: int = 2000):
     """Adam on a rotation-invariant loss; the learning rate decays geometrically from lr to lr_final.
 
     ``procrustes`` (default): distance to the nearest rotation of the targets,
@@ -122,6 +123,8 @@ def train(net: WarmStartNet, X: torch.Tensor, T: torch.Tensor, steps: int, batch
             hist.append({"step": it, "loss": tot / batch, "smoothed": run, "lr": rate,
                          "t": round(time.perf_counter() - t0, 2)})
             log(f"[train] step {it}: loss {tot / batch:.4f} (smoothed {run:.4f}) lr {rate:.2e}")
+        if checkpoint is not None and it > 0 and it % checkpoint_every == 0:
+            checkpoint(it)
     return hist
 
 
@@ -283,12 +286,19 @@ def main(argv=None):
     net = WarmStartNet(grid=COARSE, n_out=N_STATES + a.data_guards, max_batch=a.batch, seed=a.seed)
     val0 = evaluate_loss(net, X[nt:], T[nt:], a.loss)
     log(f"[train] validation loss before training {val0:.4f}")
+    base_meta = {"loss": a.loss, "n_out": N_STATES + a.data_guards, "train_geometries": nt,
+                 "val_geometries": a.val_geometries, "fine_grid": a.fine, "gamma": a.gamma, "batch": a.batch,
+                 "lr": a.lr}
+
+    def checkpoint(it):
+        save_weights(net, a.out, {**base_meta, "steps": it, "checkpoint": True})
+        log(f"[train] checkpoint at step {it}")
+
     hist = train(net, X[:nt], T[:nt], a.steps, batch=a.batch, lr=a.lr, lr_final=a.lr_final, seed=a.seed, log=log,
-                 loss=a.loss)
+                 loss=a.loss, checkpoint=checkpoint)
     val1 = evaluate_loss(net, X[nt:], T[nt:], a.loss)
     log(f"[train] validation loss after training {val1:.4f}")
-    meta = {"loss": a.loss, "n_out": N_STATES + a.data_guards, "train_geometries": nt, "val_geometries": a.val_geometries, "fine_grid": a.fine, "gamma": a.gamma,
-            "steps": a.steps, "batch": a.batch, "lr": a.lr, "val_loss_before": val0, "val_loss_after": val1}
+    meta = {**base_meta, "steps": a.steps, "val_loss_before": val0, "val_loss_after": val1}
     save_weights(net, a.out, meta)
     if a.log:
         with open(a.log, "w") as f:

@@ -358,3 +358,71 @@ def test_batch_matches_individual_plans(P):
     batch.step(psis_b, 0.3)
     for i in range(len(systems)):
         assert np.array_equal(psis_b[i].cpu().numpy(), psis_i[i].cpu().numpy())
+
+
+# ------------------------------------------------------------------ plane-pass launch shapes
+SHAPES = [(0, 0), (1, 1), (2, 1), (2, 2), (2, 3)]
+
+
+@pytest.mark.parametrize("prec,grid,ns,order", [("fp32", 64, 13, 8), ("fp64", 64, 7, 12), ("fp32", 96, 5, 6),
+                                                 ("fp32", 128, 125, 12), ("fp32", 32, 4, 4)])
+def test_plane_shapes_are_bitwise_identical(P, prec, grid, ns, order):
+    import torch
+    say("plane shapes", prec, grid, ns, order)
+    box = (12.0,) * 3
+    plan = P.Plan((grid,) * 3, box, ns, order, prec)
+    plan.set_potential(toy_potential((grid,) * 3, box))
+    psi0 = plan.new_states(W.random_states(41, ns, (grid,) * 3))
+    outs = []
+    for shape in SHAPES:
+        plan.set_plane_shape("plane_fwd", *shape)
+        plan.set_plane_shape("plane_link", *shape)
+        x = psi0.clone()
+        plan.step(x, 0.3)
+        outs.append(x.cpu())
+    for sh, o in zip(SHAPES[1:], outs[1:]):
+        assert torch.equal(o, outs[0]), sh
+    # the fused iteration (graph replay) after shape changes
+    eigs = []
+    for shape in [(0, 0), (1, 1), (2, 2)]:
+        plan.set_plane_shape("plane_fwd", *shape)
+        plan.set_plane_shape("plane_link", *shape)
+        x = psi0.clone()
+        plan.orthonormalize(x)
+        eigs.append(plan.iterate(x, 0.3)["eig"])
+    assert all(np.array_equal(e, eigs[0]) for e in eigs[1:])
+
+
+def test_autotune_and_cache(P, tmp_path):
+    import torch
+    say("autotune + cache")
+    grid, ns = 64, 9
+    box = (12.0,) * 3
+    V = toy_potential((grid,) * 3, box)
+    cache = str(tmp_path / "tune.txt")
+    plan = P.Plan((grid,) * 3, box, ns, 8, "fp32")
+    plan.set_potential(V)
+    psi0 = plan.new_states(W.random_states(5, ns, (grid,) * 3))
+    ref = psi0.clone()
+    plan.step(ref, 0.2)
+    keep = psi0.clone()
+    r = plan.autotune(psi0, 0.2, reps=1, cache=cache)
+    assert torch.equal(psi0, keep)                      # psi is read only
+    assert r["ms_per_step"]["plane_fwd"] > 0 and r["ms_per_step"]["plane_link"] > 0
+    x = psi0.clone()
+    plan.step(x, 0.2)
+    assert torch.equal(x, ref)
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and "|" in lines[0]
+    plan2 = P.Plan((grid,) * 3, box, ns, 8, "fp32")
+    plan2.set_potential(V)
+    r2 = plan2.autotune(psi0, 0.2, reps=1, cache=cache)
+    assert r2["ms_per_step"]["plane_fwd"] == -1.0       # served from the cache
+    assert r2["plane_fwd"] == r["plane_fwd"] and r2["plane_link"] == r["plane_link"]
+    from paper_0809_3739_amd import MpeError
+    with pytest.raises(MpeError):
+        plan.set_plane_shape("plane_fwd", 3, 1)
+    with pytest.raises(MpeError):
+        plan.set_plane_shape("pencil", 1, 1)
+    with pytest.raises(MpeError):
+        plan.set_plane_shape("plane_link", 1, 0)
