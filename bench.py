@@ -181,6 +181,7 @@ def main():
         "launch_shapes": plan.plane_shape(),
         "autotune_ms_per_step": None if tuned is None else tuned["ms_per_step"],
         "last_iteration": {"eig0": float(out["eig"][0]), "eig119": float(out["eig"][119]),
+                           "jacobi_sweeps": plan.last_jacobi_sweeps,
                            "max_rh": float(np.max(out["rh"][:n_states]))},
     }
     if args.solve:

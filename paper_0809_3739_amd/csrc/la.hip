@@ -488,7 +488,7 @@ struct Mfma<float> {
 };
 
 template <typename F, typename MT, bool WITH_H, int NT>
-__global__ __launch_bounds__(256) void rotate_kernel(RotateArgs r) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void rotate_kernel(RotateArgs r) {
   __shared__ MT cT[MAXM * MAXM];      // cT[j * mp + i] = C[i][j]
   __shared__ double thl[MAXM];
   __shared__ double rs[4][MAXM];
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(256) void rotate_kernel(RotateArgs r) {
     const bool pok = p < p_end;
     // B operands in groups of KG k-steps; the next group's loads are issued
     // before the current group's MFMAs so their latency hides behind them.
-    constexpr int KG = 4;
+    constexpr int KG = 2;
     MT b[KG], bh[KG], nb[KG], nbh[KG];
     auto load_group = [&](int k0, MT (&x)[KG], MT (&xh)[KG]) {
 #pragma unroll
@@ -543,6 +543,7 @@ __global__ __launch_bounds__(256) void rotate_kernel(RotateArgs r) {
     acc_t ap[NT], ah[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) ap[t] = ah[t] = acc_t{0, 0, 0, 0};
+#pragma unroll 1
     for (int k0 = 0; k0 < nk; k0 += KG) {
       if (k0 + KG < nk) load_group(k0 + KG, nb, nbh);
 #pragma unroll
