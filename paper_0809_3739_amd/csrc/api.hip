@@ -1151,6 +1151,11 @@ struct mpe_batch_s {
   std::vector<void*> g_psi;
   hipEvent_t ev_in = nullptr;
   int launches = 0;
+  // branches of the captured iteration: the per-system overlaps, small dense
+  // solves and rotations of different systems run on these streams side by side
+  std::vector<hipStream_t> br;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
 };
 
 namespace {
@@ -1281,26 +1286,38 @@ mpe_status enqueue_batch_iterate(mpe_batch b, void* const* psi, hipStream_t st) 
     mpe_status s = enqueue_group_h(b, g, st);
     if (s != MPE_OK) return s;
   }
+  // fork: system i's chain goes to branch i % nbr
+  const int nbr = (int)b->br.size();
+  if (nbr > 0) {
+    BHIPCHK(b, hipEventRecord(b->ev_fork, st));
+    for (auto s2 : b->br) BHIPCHK(b, hipStreamWaitEvent(s2, b->ev_fork, 0));
+  }
   for (int i = 0; i < b->count; ++i) {
     mpe_plan p = b->plans[i];
     hipStream_t keep = p->st;
-    p->st = st;
+    const hipStream_t si = nbr > 0 ? b->br[i % nbr] : st;
+    p->st = si;
     const void* X[3] = {p->phi, p->phi, psi[i]};
     const void* Y[3] = {p->phi, p->hphi, p->phi};
     mpe_status s = run_gram(p, X, Y, 3, p->S());
     if (s == MPE_OK) {
-      hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, p->re(), p->reperp(), st);
+      hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, p->re(), p->reperp(), si);
       if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));
     }
     if (s == MPE_OK) s = run_small_dense(p, SD_RR);
     if (s == MPE_OK) s = run_rotate(p, p->phi, p->hphi, psi[i], p->hphi);
     if (s == MPE_OK) {
-      hipError_t e = hipMemcpyAsync(p->host_res, p->res, p->res_bytes, hipMemcpyDeviceToHost, st);
+      hipError_t e = hipMemcpyAsync(p->host_res, p->res, p->res_bytes, hipMemcpyDeviceToHost, si);
       if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));
     }
     p->st = keep;
     if (s != MPE_OK) return bfail(b, s, "system " + std::to_string(i) + ": " + p->err);
     b->launches += 7;
+  }
+  // join
+  for (int j = 0; j < nbr; ++j) {
+    BHIPCHK(b, hipEventRecord(b->ev_join[j], b->br[j]));
+    BHIPCHK(b, hipStreamWaitEvent(st, b->ev_join[j], 0));
   }
   return MPE_OK;
 }
@@ -1321,6 +1338,9 @@ mpe_status mpe_batch_destroy(mpe_batch b) {
     if (p) mpe_plan_destroy(p);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->gst) (void)hipStreamDestroy(b->gst);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  for (auto e : b->ev_join) (void)hipEventDestroy(e);
+  for (auto s2 : b->br) (void)hipStreamDestroy(s2);
   delete b;
   return MPE_OK;
 }
@@ -1371,9 +1391,25 @@ mpe_status mpe_batch_create(mpe_batch* out, int32_t count, const mpe_system_desc
     }
   }
   if (hipStreamCreateWithFlags(&b->gst, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess) {
     mpe_batch_destroy(b);
     return MPE_ERR_DEVICE;
+  }
+  const int nbr = std::min(b->count, 8);
+  for (int j = 0; nbr > 1 && j < nbr; ++j) {   // default-priority streams
+    hipStream_t s2 = nullptr;
+    hipEvent_t e2 = nullptr;
+    if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
+      mpe_batch_destroy(b);
+      return MPE_ERR_DEVICE;
+    }
+    b->br.push_back(s2);
+    if (hipEventCreateWithFlags(&e2, hipEventDisableTiming) != hipSuccess) {
+      mpe_batch_destroy(b);
+      return MPE_ERR_DEVICE;
+    }
+    b->ev_join.push_back(e2);
   }
   *out = b;
   return MPE_OK;

@@ -337,9 +337,11 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   for (int i = tid; i < m; i += SD_THREADS) dmax = fmax(dmax, fabs(A(i, i)));
   const double floor_abs = 32.0 * 2.220446049250313e-16 * fmax(block_max(dmax, red), 1e-300) / d.tol;
   const double rot_tol = 0.125 * d.tol;
-  // eigenvectors accumulate in U (global, L2 resident): U <- U J each step
-  double* U = d.rot;
-  for (int e = tid; e < m * m; e += SD_THREADS) U[(e / m) * (long)d.mp + e % m] = (e / m == e % m) ? 1.0 : 0.0;
+  // eigenvectors accumulate in U (global, L2 resident), stored by columns
+  // (Ut[c * mp + r] = U[r][c]) so that a rotation of columns p, q is two
+  // contiguous sweeps: U <- U J each step
+  double* Ut = d.rot;
+  for (int e = tid; e < m * m; e += SD_THREADS) Ut[(e / m) * (long)d.mp + e % m] = (e / m == e % m) ? 1.0 : 0.0;
   __syncthreads();
   int sweep = 0;
   bool converged = false;
@@ -390,16 +392,17 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
       }
       __syncthreads();
       if (step_active[cur]) {   // uniform
-        // columns p, q of U (rows in parallel; a row's pairs are neighbouring threads)
+        // columns p, q of U (neighbouring threads take neighbouring rows of one pair)
         for (int e = tid; e < half * m; e += SD_THREADS) {
-          const int r = e / half, k = e - r * half;
+          const int k = e / m, r = e - k * m;
           const int pk = pq[k][0], qk = pq[k][1];
           if (qk < m) {
             const double ck = cs[k][0], sk = cs[k][1];
-            double* ur = U + (long)r * d.mp;
-            const double up = ur[pk], uq = ur[qk];
-            ur[pk] = ck * up - sk * uq;
-            ur[qk] = sk * up + ck * uq;
+            double* up_ = Ut + (long)pk * d.mp + r;
+            double* uq_ = Ut + (long)qk * d.mp + r;
+            const double up = *up_, uq = *uq_;
+            *up_ = ck * up - sk * uq;
+            *uq_ = sk * up + ck * uq;
           }
         }
         for (int e = tid; e < half * half; e += SD_THREADS) {
@@ -444,7 +447,7 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   __threadfence_block();
   __syncthreads();
   // U into LDS (A is no longer needed)
-  for (int e = tid; e < m * m; e += SD_THREADS) A(e / m, e % m) = U[(e / m) * (long)d.mp + e % m];
+  for (int e = tid; e < m * m; e += SD_THREADS) A(e % m, e / m) = Ut[(e / m) * (long)d.mp + e % m];
   __syncthreads();
   stamp(d, 4);
   // C = L^-T U
@@ -488,7 +491,8 @@ struct Mfma<float> {
 };
 
 template <typename F, typename MT, bool WITH_H, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void rotate_kernel(RotateArgs r) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) == 4 ? 2 : 1))) void rotate_kernel(
+    RotateArgs r) {
   __shared__ MT cT[MAXM * MAXM];      // cT[j * mp + i] = C[i][j]
   __shared__ double thl[MAXM];
   __shared__ double rs[4][MAXM];
