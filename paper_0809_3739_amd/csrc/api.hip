@@ -131,6 +131,8 @@ struct mpe_plan_s {
 
   // workspace
   void* W = nullptr;           // K chains x m states x spec complex
+  void* tailbuf = nullptr;     // split tail: K chains x m states x N real (when tail_split)
+  bool split_tail = false;
   void* phi = nullptr;         // m x N
   void* hphi = nullptr;        // m x N
   double* V64 = nullptr;       // N
@@ -370,17 +372,34 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
   }
   Timer t;
   tic(p, t, MPE_KC_PLANE_TAIL);
-  HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
-           PlaneArgs a = plane_base(p);
-           a.spec = chain_spec(p, 0);
-           a.chain_stride = (long)p->m * p->spec;
-           a.fac = p->fac;
-           a.real_out = dst;
-           a.K = p->K;
-           for (int k = 0; k < p->K; ++k) a.coef[k] = c[k];
-           a.state0 = s0;
-           return launch_plane(p->dbl, PM_TAIL, p->nx, a, p->nz, cnt, p->st);
-         }));
+  if (p->split_tail) {
+    // each chain leaves through its own pass, then the float64 combination
+    for (int k = 0; k < p->K; ++k) {
+      void* out_k = (char*)p->tailbuf + (size_t)k * p->m * p->N * f;
+      HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
+               PlaneArgs a = plane_base(p);
+               a.spec = chain_spec(p, k);
+               a.fac = p->fac;
+               a.fac_index = 2 * k + 1;
+               a.real_out = out_k;
+               a.state0 = s0;
+               return launch_plane(p->dbl, PM_OUT, p->nx, a, p->nz, cnt, p->st);
+             }));
+    }
+    HIPCHK(p, launch_combine(p->dbl, p->tailbuf, (long)p->m * p->N, p->K, c, dst, (long)p->m * p->N, p->st));
+  } else {
+    HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
+             PlaneArgs a = plane_base(p);
+             a.spec = chain_spec(p, 0);
+             a.chain_stride = (long)p->m * p->spec;
+             a.fac = p->fac;
+             a.real_out = dst;
+             a.K = p->K;
+             for (int k = 0; k < p->K; ++k) a.coef[k] = c[k];
+             a.state0 = s0;
+             return launch_plane(p->dbl, PM_TAIL, p->nx, a, p->nz, cnt, p->st);
+           }));
+  }
   toc(p, t);
   return MPE_OK;
 }
@@ -672,7 +691,7 @@ mpe_status mpe_plan_destroy(mpe_plan p) {
   drop_graph(p);
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->gst) (void)hipStreamDestroy(p->gst);
-  void* bufs[] = {p->W, p->phi, p->hphi, p->V64, p->Vf, p->fac, p->kin, p->hk, p->roots,
+  void* bufs[] = {p->W, p->tailbuf, p->phi, p->hphi, p->V64, p->Vf, p->fac, p->kin, p->hk, p->roots,
                   p->partials, p->mats, p->rot, p->res, p->ticks};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -765,6 +784,8 @@ mpe_status mpe_plan_create(mpe_plan* out, const int32_t grid[3], const double bo
             alloc((void**)&p->mats, 5 * (size_t)p->mp * p->mp * sizeof(double)) &&
             alloc((void**)&p->rot, p->rot_count * 4 * sizeof(double)) && alloc((void**)&p->res, p->res_bytes) &&
             alloc((void**)&p->ticks, 8 * sizeof(long long));
+  p->split_tail = tail_split(p->dbl, p->nx);
+  if (ok && p->split_tail) ok = alloc(&p->tailbuf, (size_t)p->K * m * N * f);
   if (!ok) {
     mpe_plan_destroy(p);
     return MPE_ERR_OUT_OF_MEMORY;

@@ -25,6 +25,18 @@ struct alignas(2 * sizeof(F)) cx {
 template <typename T>
 using gp = T __attribute__((address_space(1)))*;
 
+// Value of the neighbouring lane (lane ^ 1) through a DPP quad permutation
+// [1, 0, 3, 2] (a VALU operand modifier, no LDS traffic).
+__device__ __forceinline__ float lane_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_xor1(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Complex loads and stores through global pointers, as one 2-element vector
 // access (dwordx2 / dwordx4).
 template <typename F>

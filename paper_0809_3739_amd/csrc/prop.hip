@@ -16,6 +16,8 @@
 //   PM_TAIL  K half spectra -> sum_k c_k * factor_k * real rows, float64
 //            accumulation in registers, one rounding on store
 //   PM_HTAIL half spectrum -> real rows + V*phi   (H application)
+//   PM_OUT   half spectrum -> real rows x exp(-tau_k V/2) of one chain (the
+//            tail of a chain when the fused tail pass does not fit)
 #include <hip/hip_runtime.h>
 
 #include "fft.hpp"
@@ -153,7 +155,11 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
   const int tx = tid % TX, rloc = tid / TX;
   // column phase mapping
   const int f = tid % NCF, ty = tid / NCF;
-  const bool cact = ty < TY;                       // threads beyond NCF*TY idle in the column phase
+  // threads beyond NCF*TY idle in the column phase; rows beyond NY in the row phase.
+  // The checks stay run-time even where every thread is active: folded, they let
+  // the compiler hoist loads across the transforms and raise register pressure.
+  constexpr bool ALL_COLS = false, ALL_ROWS = false;
+  const bool cact = ALL_COLS || ty < TY;
   const int g = f >> 1, h = f & 1;
   const bool packed = (g == 0 && h == 0);
   const int col = (g == 0) ? (h ? HALF : 0) : (h ? LX - g : g);   // LDS / spectrum column
@@ -192,7 +198,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
     const cx<F> w = wk(col);
 #pragma unroll
     for (int m = 0; m < EY; ++m) {
-      const cx<F> pr{__shfl_xor(v[m].x, 1), __shfl_xor(v[m].y, 1)};
+      const cx<F> pr{lane_xor1(v[m].x), lane_xor1(v[m].y)};
       cx<F> zv;
       if (packed) {
         zv = cx<F>{v[m].x + v[m].y, v[m].x - v[m].y};         // X0 = Re, X_LX = Im
@@ -321,7 +327,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
 #pragma unroll
         for (int rr = 0; rr < XR; ++rr) {
           const int row = rr * RPR + rloc;
-          const bool act = row < NY;
+          const bool act = ALL_ROWS || row < NY;
           const int rowc = act ? row : 0;
           cx<F> v[EX];
 #pragma unroll
@@ -355,7 +361,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
 #pragma unroll
         for (int rr = 0; rr < XR; ++rr) {
           const int row = rr * RPR + rloc;
-          const bool act = row < NY;
+          const bool act = ALL_ROWS || row < NY;
           const int rowc = act ? row : 0;
           cx<F> v[EX];
           if (act) {
@@ -387,8 +393,8 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
       P = Pn;
     }
   } else if constexpr (MODE == PM_TAIL) {
-    const int z = blockIdx.x;
-    const Ptrs P = ptrs_of((long)blockIdx.y + a.state0);
+    const int z = blockIdx.y;
+    const Ptrs P = ptrs_of((long)blockIdx.x + a.state0);
     const long z_real = (long)z * plane_real, z_spec = (long)z * plane_spec;
     gp<cx<F>> spec = P.spec;
     gp<const F> facb = P.facb;
@@ -419,7 +425,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
 #pragma unroll
       for (int rr = 0; rr < XR; ++rr) {
         const int row = rr * RPR + rloc;
-        const bool act = row < NY;
+        const bool act = ALL_ROWS || row < NY;
         const int rowc = act ? row : 0;
         cx<F> v[EX];
         if (act) {
@@ -452,7 +458,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
         for (int m = 0; m < EX; ++m) gstore<F>(d2 + tx + TX * m, cx<F>{(F)acc[rr][m][0], (F)acc[rr][m][1]});
       }
     }
-  } else {  // PM_HTAIL
+  } else {  // PM_HTAIL, PM_OUT
     const int z = blockIdx.x;
     const Ptrs P = ptrs_of((long)blockIdx.y + a.state0);
     const long z_real = (long)z * plane_real, z_spec = (long)z * plane_spec;
@@ -463,12 +469,12 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
     gp<F> rout = P.rout;
     column_inverse(spec + z_spec);
     gp<const F> __restrict__ phi = rin + z_real;
-    gp<const F> __restrict__ V = facb + z_real;
+    gp<const F> __restrict__ V = (MODE == PM_OUT ? P.facz : facb) + z_real;
     gp<F> __restrict__ dst = rout + z_real;
 #pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
-      const bool act = row < NY;
+      const bool act = ALL_ROWS || row < NY;
       const int rowc = act ? row : 0;
       cx<F> v[EX];
       if (act) {
@@ -480,10 +486,18 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
         gp<const cx<F>> p2 = reinterpret_cast<gp<const cx<F>>>(phi + (long)row * NX);
         gp<const cx<F>> v2 = reinterpret_cast<gp<const cx<F>>>(V + (long)row * NX);
         gp<cx<F>> d2 = reinterpret_cast<gp<cx<F>>>(dst + (long)row * NX);
+        if constexpr (MODE == PM_OUT) {
 #pragma unroll
-        for (int m = 0; m < EX; ++m) {
-          const cx<F> pv = gload<F>(p2 + tx + TX * m), wv = gload<F>(v2 + tx + TX * m);
-          gstore<F>(d2 + tx + TX * m, cx<F>{v[m].x + wv.x * pv.x, v[m].y + wv.y * pv.y});
+          for (int m = 0; m < EX; ++m) {
+            const cx<F> wv = gload<F>(v2 + tx + TX * m);
+            gstore<F>(d2 + tx + TX * m, cx<F>{v[m].x * wv.x, v[m].y * wv.y});
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < EX; ++m) {
+            const cx<F> pv = gload<F>(p2 + tx + TX * m), wv = gload<F>(v2 + tx + TX * m);
+            gstore<F>(d2 + tx + TX * m, cx<F>{v[m].x + wv.x * pv.x, v[m].y + wv.y * pv.y});
+          }
         }
       }
     }
@@ -582,12 +596,17 @@ static hipError_t launch_plane_n(int mode, const PlaneArgs& a, int nz, int nstat
       return hipGetLastError();
     }
   }
-  dim3 grid(nz, nstates);
+  // z planes fastest (neighbouring work-groups stream neighbouring planes of one
+  // state), except in the tail pass: there states go fastest, so the work-groups
+  // in flight share a few z planes and the 2K potential-factor planes they read
+  // stay in every XCD's L2 while the states stream past
+  dim3 grid(nz, nstates), grid_t(nstates, nz);
   switch (mode) {
     case PM_FWD: hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD, 0>), grid, block, 0, st, a); break;
     case PM_LINK: hipLaunchKernelGGL((plane_kernel<F, N, PM_LINK, 0>), grid, block, 0, st, a); break;
-    case PM_TAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_TAIL, 0>), grid, block, 0, st, a); break;
+    case PM_TAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_TAIL, 0>), grid_t, block, 0, st, a); break;
     case PM_HTAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_HTAIL, 0>), grid, block, 0, st, a); break;
+    case PM_OUT: hipLaunchKernelGGL((plane_kernel<F, N, PM_OUT, 0>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -611,6 +630,47 @@ bool plane_supported(int is_double, int nx, int ny) {
     case 192: return !is_double;   // 192 x 97 complex doubles exceed the 160 KB LDS
     default: return false;
   }
+}
+
+bool tail_split(int is_double, int nx) { return is_double ? nx >= 128 : nx >= 192; }
+
+struct Coefs {
+  double c[MAX_K];
+};
+
+// dst = sum_k c_k tmp_k (float64 sum, one rounding on store), 4 elements per thread
+template <typename F>
+__global__ __launch_bounds__(256) void combine_kernel(const F* __restrict__ tmp, long stride, int K, Coefs c,
+                                                      F* __restrict__ dst, long n) {
+  const long i0 = ((long)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (i0 >= n) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int cnt = (int)(n - i0 < 4 ? n - i0 : 4);
+  for (int k = 0; k < K; ++k) {
+    const F* t = tmp + k * stride + i0;
+    const double ck = c.c[k];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (e < cnt) acc[e] += ck * (double)t[e];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (e < cnt) dst[i0 + e] = (F)acc[e];
+}
+
+hipError_t launch_combine(int is_double, const void* tmp, long stride, int K, const double* coef, void* dst, long n,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  Coefs c;
+  for (int k = 0; k < MAX_K; ++k) c.c[k] = k < K ? coef[k] : 0.0;
+  const dim3 grid((unsigned)((n + 1023) / 1024));
+  if (is_double)
+    hipLaunchKernelGGL(combine_kernel<double>, grid, dim3(256), 0, st, (const double*)tmp, stride, K, c,
+                       (double*)dst, n);
+  else
+    hipLaunchKernelGGL(combine_kernel<float>, grid, dim3(256), 0, st, (const float*)tmp, stride, K, c,
+                       (float*)dst, n);
+  return hipGetLastError();
 }
 
 bool pencil_supported(int nz) {

@@ -6,7 +6,7 @@ namespace mpe {
 
 constexpr int MAX_K = 6;  // order 2K <= 12
 
-enum PlaneMode { PM_FWD = 0, PM_LINK = 1, PM_TAIL = 2, PM_HTAIL = 3 };
+enum PlaneMode { PM_FWD = 0, PM_LINK = 1, PM_TAIL = 2, PM_HTAIL = 3, PM_OUT = 4 };
 enum PencilKind { PK_EXP = 0, PK_ADD = 1 };
 
 // Per-state addresses for launches that cover states of several systems of
@@ -68,6 +68,13 @@ struct PencilArgs {
 };
 
 bool plane_supported(int is_double, int nx, int ny);
+// Whether the fused tail pass (all K chains combined in float64 registers) runs
+// out of registers for this plane; then each chain leaves the tail on its own
+// (PM_OUT into a real buffer) and launch_combine forms sum_k c_k x_k.
+bool tail_split(int is_double, int nx);
+// dst[i] = sum_k coef[k] tmp[k * stride + i], i < n, accumulated in float64
+hipError_t launch_combine(int is_double, const void* tmp, long stride, int K, const double* coef, void* dst, long n,
+                          hipStream_t st);
 bool pencil_supported(int nz);
 hipError_t launch_plane(int is_double, int mode, int nx, const PlaneArgs& a, int nz, int nstates, hipStream_t st);
 hipError_t launch_pencil(int is_double, int kind, int nz, const PencilArgs& a, int nstates, hipStream_t st);

@@ -298,6 +298,28 @@ def test_full_size_c60_step_sampled(P, prec):
         assert err < tol
 
 
+def test_c60_192_step_sampled(P):
+    """192^3 C60-like cage (the precision-at-scale configuration), 120 states,
+    order 12, float32: the tail leaves chain by chain and is combined in float64;
+    one sampled state against the oracle, and the fused 128^3 and split paths
+    agree in structure (same tolerance as every float32 step)."""
+    s = W.c60_system(192, 32.0, 120)
+    m = 120
+    say("192^3 step", s.grid, m)
+    plan = P.Plan(s.grid, s.box, 120, 12, "fp32")
+    plan.set_potential(s.V)
+    rng_states = W.random_states(3, m, s.grid)
+    psi = plan.new_states(rng_states)
+    plan.step(psi, 0.5)
+    j = 77
+    got = psi[j:j + 1].cpu().numpy().astype(np.float64)
+    ref = oracle.mpe_apply(rounded(rng_states[j:j + 1], "fp32"), s.V, 0.5, 6, s.grid, s.box)
+    err = rel_err(got, ref)
+    tol = STEP32 * sum_abs_c(12)
+    say(f"  state {j} rel err {err:.3e} tol {tol:.1e}")
+    assert err < tol
+
+
 def test_graph_replay_matches_eager(P):
     """mpe_iterate replayed from a captured hipGraph equals the eager launches bitwise,
     over several replays with eager work, a dt change and host syncs in between."""
