@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--dt", type=float, default=0.5)
     ap.add_argument("--states-per-launch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--gemm", default="fp64", choices=["fp64", "fp32"],
+                    help="overlap GEMMs on float64 MFMA (default) or float32 MFMA (float32 plans)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default plane-pass shapes instead of timing the candidates first")
     ap.add_argument("--solve", action="store_true",
@@ -168,6 +170,8 @@ def main():
     s = W.c60_system(args.grid, 32.0, n_states)
     plan = P.Plan(s.grid, s.box, n_states, args.order, args.precision, n_guard=n_guard)
     plan.set_potential(s.V)
+    if args.gemm != "fp64":
+        plan.set_gemm_precision(args.gemm)
     if args.states_per_launch:
         plan.set_states_per_launch(args.states_per_launch)
     psi = plan.new_states(W.random_states(0, m, s.grid))
@@ -229,7 +233,7 @@ def main():
         "config": {"workload": f"c60-like gaussian cage {args.grid}^3, 120+5 states, MPE order {args.order}, "
                                f"one fused iteration per step",
                    "grid": args.grid, "states": m, "order": args.order, "dt": args.dt,
-                   "precision": args.precision, "parallelism": "single GPU"},
+                   "precision": args.precision, "overlap_gemm": args.gemm, "parallelism": "single GPU"},
         "phases_ms_per_step": {"T_pro": round(t_pro, 3), "T_ort": round(t_ort, 3),
                                **{k: round(v[0] / args.steps, 3) for k, v in kt.items() if v[1]}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -170,6 +170,17 @@ mpe_status mpe_set_states_per_launch(mpe_plan p, int32_t states);
  * (persistent modes). */
 mpe_status mpe_set_plane_shape(mpe_plan p, int32_t kernel_class, int32_t mode, int32_t blocks_per_cu);
 
+/* Precision of the overlap GEMMs (S = Phi Phi^T, Hs, the variance overlaps):
+ * MPE_GEMM_FP64 (default): float64 MFMA on the states (exact products of
+ * float32 states); MPE_GEMM_FP32 (float32 plans only): float32 MFMA with float32
+ * accumulation over slabs of 32 points and float64 sums across slabs and
+ * chunks -- the float32 half of the precision split; overlaps then carry
+ * ~1e-7 relative error, so the Cholesky pivot test becomes 1e-5 of the
+ * diagonal.  The rotation of float32 plans always runs on float32 MFMA.
+ * MPE_ERR_UNSUPPORTED for MPE_GEMM_FP32 on a float64 plan. */
+enum { MPE_GEMM_FP64 = 0, MPE_GEMM_FP32 = 1 };
+mpe_status mpe_set_gemm_precision(mpe_plan p, int32_t mode);
+
 /* Current shapes: shape[4] = {fwd mode, fwd blocks_per_cu, link mode, link blocks_per_cu}. */
 mpe_status mpe_get_plane_shape(mpe_plan p, int32_t* shape);
 

@@ -51,6 +51,7 @@ SIGNATURES = {
     "mpe_set_states_per_launch": (C.c_int, [_vp, _i32]),
     "mpe_set_plane_shape": (C.c_int, [_vp, _i32, _i32, _i32]),
     "mpe_get_plane_shape": (C.c_int, [_vp, C.POINTER(_i32)]),
+    "mpe_set_gemm_precision": (C.c_int, [_vp, _i32]),
     "mpe_autotune": (C.c_int, [_vp, _vp, C.c_double, _i32, C.c_char_p, _dp]),
     "mpe_set_graph": (C.c_int, [_vp, _i32]),
     "mpe_last_jacobi_sweeps": (C.c_int32, [_vp]),

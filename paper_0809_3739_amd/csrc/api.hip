@@ -165,6 +165,7 @@ struct mpe_plan_s {
   int pbpc[2] = {0, 0};
   int shape_ver = 0;
   int n_cu = 0;
+  int gemm = 0;                 // overlap GEMMs: 0 = float64 MFMA, 1 = float32 MFMA (float32 plans)
   int max_sweeps = 60;
   double jacobi_tol = 1e-13;
   double pivot_tol = 1e-13;
@@ -482,7 +483,8 @@ mpe_status run_gram(mpe_plan p, const void* const* X, const void* const* Y, int 
   g.mp = p->mp;
   Timer t;
   tic(p, t, MPE_KC_GRAM);
-  HIPCHK(p, launch_gram(p->dbl, g, nprod, nch, p->st));
+  if (!p->dbl && p->gemm == 1) HIPCHK(p, launch_gram32(g, nprod, nch, p->st));
+  else HIPCHK(p, launch_gram(p->dbl, g, nprod, nch, p->st));
   HIPCHK(p, launch_reduce(p->partials, nch, (long)p->mp * p->mp, nprod, out0, p->st));
   toc(p, t);
   return MPE_OK;
@@ -1012,6 +1014,20 @@ mpe_status mpe_set_plane_shape(mpe_plan p, int32_t kernel_class, int32_t mode, i
   p->pmode[c] = mode;
   p->pbpc[c] = mode > 0 ? blocks_per_cu : 0;
   p->shape_ver++;
+  return MPE_OK;
+}
+
+mpe_status mpe_set_gemm_precision(mpe_plan p, int32_t mode) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (mode != MPE_GEMM_FP64 && mode != MPE_GEMM_FP32)
+    return fail(p, MPE_ERR_INVALID_ARGUMENT, "mode must be MPE_GEMM_FP64 or MPE_GEMM_FP32");
+  if (mode == MPE_GEMM_FP32 && p->dbl)
+    return fail(p, MPE_ERR_UNSUPPORTED, "float32 overlap GEMMs are for float32 plans");
+  p->gemm = mode == MPE_GEMM_FP32 ? 1 : 0;
+  // overlaps now carry ~1e-7 relative error: a pivot below 1e-5 of its diagonal
+  // marks linearly dependent states
+  p->pivot_tol = p->gemm ? 1e-5 : 1e-13;
+  p->shape_ver++;   // re-capture the iteration graph
   return MPE_OK;
 }
 

@@ -19,6 +19,7 @@
 namespace mpe {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Lane layout of v_mfma_f64_16x16x4f64 (one block, 64 lanes), measured on gfx950:
 //   A (16x4) : lane l holds A[l % 16][l / 16]
@@ -138,6 +139,99 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
         const int i = tiv[t] * 16 + drow(lane, r), j = tjv[t] * 16 + (lane & 15);
         out[(long)i * mp + j] = acc[t][r];
         if (SYM && tiv[t] != tjv[t]) out[(long)j * mp + i] = acc[t][r];
+      }
+    }
+  }
+}
+
+// Float32-MFMA variant for float32 states (the precision split of the overlap
+// GEMMs): 512 threads (8 waves), points staged as float, v_mfma_f32_16x16x4f32
+// with float32 accumulation over one slab of GSLAB points, then added into
+// float64 per-tile sums (one rounding per 32 products), float64 partials out.
+template <int NT, bool SYM>
+__global__ __launch_bounds__(512) void gram32_partial_kernel(GramArgs g) {
+  constexpr int W = 8;
+  constexpr int mp = NT * 16;
+  constexpr int NTILE = GramTiles<NT, SYM>::count;
+  constexpr int TPW = (NTILE + W - 1) / W;
+  constexpr int PER = (mp * GSLAB + 511) / 512;
+  __shared__ float xs[GSLAB][GLD];
+  __shared__ float ys[SYM ? 1 : GSLAB][SYM ? 1 : GLD];
+  const int prod = blockIdx.y;
+  const float* __restrict__ X = reinterpret_cast<const float*>(g.X[prod]);
+  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y[prod]);
+  const int m = g.m;
+  const long N = g.N;
+  const long p_begin = (long)blockIdx.x * g.chunk;
+  const long p_end = min(N, p_begin + g.chunk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int tiv[TPW], tjv[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int u = wave + W * t;
+    tile_coords(u < NTILE ? u : 0, NT, SYM, tiv[t], tjv[t]);
+  }
+  d4 sum[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) sum[t] = d4{0.0, 0.0, 0.0, 0.0};
+  float px[PER], py[PER];
+  auto load = [&](long p0) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 512 * r;
+      const int st = e / GSLAB, q = e - st * GSLAB;
+      const long p = p0 + q;
+      const bool ok = e < mp * GSLAB && st < m && p < p_end;
+      px[r] = ok ? X[(long)st * N + p] : 0.f;
+      if (!SYM) py[r] = ok ? Y[(long)st * N + p] : 0.f;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 512 * r;
+      if (e < mp * GSLAB) {
+        const int st = e / GSLAB, q = e - st * GSLAB;
+        xs[q][st] = px[r];
+        if (!SYM) ys[q][st] = py[r];
+      }
+    }
+  };
+  load(p_begin);
+  for (long p0 = p_begin; p0 < p_end; p0 += GSLAB) {
+    stage();
+    __syncthreads();
+    if (p0 + GSLAB < p_end) load(p0 + GSLAB);
+    f4 acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < GSLAB; k0 += 4) {
+      const int kq = k0 + (lane >> 4);
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        if (TPW * W == NTILE || wave + W * t < NTILE) {
+          const float a = xs[kq][tiv[t] * 16 + (lane & 15)];
+          const float b = SYM ? xs[kq][tjv[t] * 16 + (lane & 15)] : ys[kq][tjv[t] * 16 + (lane & 15)];
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sum[t][r] += (double)acc[t][r];
+    __syncthreads();
+  }
+  double* out = g.partials + ((long)prod * gridDim.x + blockIdx.x) * (long)mp * mp;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    if (wave + W * t < NTILE) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = tiv[t] * 16 + 4 * (lane >> 4) + r, j = tjv[t] * 16 + (lane & 15);   // f32 D layout
+        out[(long)i * mp + j] = sum[t][r];
+        if (SYM && tiv[t] != tjv[t]) out[(long)j * mp + i] = sum[t][r];
       }
     }
   }
@@ -470,7 +564,6 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
 // rotation of float32 states then loses nothing beyond float32 storage).
 // A strip's B operands are loaded in one go before its MFMA chain.
 
-typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <typename MT>
 struct Mfma;
@@ -647,6 +740,36 @@ static hipError_t launch_gram_t(const GramArgs& g, int nprod, int nchunks, hipSt
 
 // Products with X == Y (overlaps of one block with itself) run as symmetric
 // launches; the others as general ones.  Partials land in g.partials[prod].
+template <bool SYM>
+static hipError_t launch_gram32_t(const GramArgs& g, int nchunks, hipStream_t st) {
+  dim3 grid(nchunks, 1), block(512);
+  switch (g.mp / 16) {
+    case 1: hipLaunchKernelGGL((gram32_partial_kernel<1, SYM>), grid, block, 0, st, g); break;
+    case 2: hipLaunchKernelGGL((gram32_partial_kernel<2, SYM>), grid, block, 0, st, g); break;
+    case 3: hipLaunchKernelGGL((gram32_partial_kernel<3, SYM>), grid, block, 0, st, g); break;
+    case 4: hipLaunchKernelGGL((gram32_partial_kernel<4, SYM>), grid, block, 0, st, g); break;
+    case 5: hipLaunchKernelGGL((gram32_partial_kernel<5, SYM>), grid, block, 0, st, g); break;
+    case 6: hipLaunchKernelGGL((gram32_partial_kernel<6, SYM>), grid, block, 0, st, g); break;
+    case 7: hipLaunchKernelGGL((gram32_partial_kernel<7, SYM>), grid, block, 0, st, g); break;
+    case 8: hipLaunchKernelGGL((gram32_partial_kernel<8, SYM>), grid, block, 0, st, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gram32(const GramArgs& g, int nprod, int nchunks, hipStream_t st) {
+  for (int i = 0; i < nprod; ++i) {
+    GramArgs one = g;
+    one.X[0] = g.X[i];
+    one.Y[0] = g.Y[i];
+    one.partials = g.partials + (long)i * nchunks * g.mp * g.mp;
+    const hipError_t e = g.X[i] == g.Y[i] ? launch_gram32_t<true>(one, nchunks, st)
+                                          : launch_gram32_t<false>(one, nchunks, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_gram(int is_double, const GramArgs& g, int nprod, int nchunks, hipStream_t st) {
   for (int i = 0; i < nprod; ++i) {
     GramArgs one = g;

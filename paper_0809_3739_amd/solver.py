@@ -143,6 +143,10 @@ class Plan:
         kc = _lib.KERNEL_CLASSES.index(kernel_class)
         self._check(self.lib.mpe_set_plane_shape(self.h, kc, int(mode), int(blocks_per_cu)))
 
+    def set_gemm_precision(self, mode: str):
+        """Overlap GEMMs in "fp64" (default) or "fp32" MFMA (float32 plans)."""
+        self._check(self.lib.mpe_set_gemm_precision(self.h, {"fp64": 0, "fp32": 1}[mode]))
+
     def plane_shape(self) -> dict:
         buf = (C.c_int32 * 4)()
         self._check(self.lib.mpe_get_plane_shape(self.h, buf))

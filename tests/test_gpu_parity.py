@@ -176,6 +176,62 @@ def test_rayleigh_ritz_matches_oracle(P, prec, m, grid):
     assert np.allclose(rh[sep], rh_ref[sep], rtol=1e-6 if prec == "fp64" else 1e-2, atol=1e-20)
 
 
+@pytest.mark.parametrize("m,grid", [(20, (32, 32, 32)), (125, (16, 16, 16))])
+def test_float32_overlap_gemms(P, m, grid):
+    """Float32 plans with the float32-MFMA overlap GEMMs: orthonormality and Ritz
+    values against the oracle at the float32 bars (overlap errors ~1e-7 relative,
+    well inside them), and rank deficiency still reported.  Cholesky QR loses
+    orthonormality as cond(Phi)^2 times the overlap error, so an ill-conditioned
+    start (125 smoothed states on 16^3 points) takes a second pass, as the
+    solver's iterations do anyway."""
+    say("fp32 overlap gemms", m, grid)
+    box = (10.0, 10.0, 10.0)
+    V = toy_potential(grid, box)
+    phi = W.random_states(31, m, grid)
+    for _ in range(3):
+        phi = oracle.t2(phi, V, 0.3, grid, box)
+    plan = P.Plan(grid, box, m, 2, "fp32")
+    plan.set_potential(V)
+    plan.set_gemm_precision("fp32")
+    psi = plan.new_states(phi)
+    plan.orthonormalize(psi)
+    plan.orthonormalize(psi)
+    g = psi.cpu().numpy().astype(np.float64).reshape(m, -1)
+    ortho = np.max(np.abs(g @ g.T - np.eye(m)))
+    say("  orthonormality after two passes", ortho)
+    assert ortho < 1e-5
+    Psi0, _, _ = oracle.cholesky_orthonormalize(phi)
+    Psi0 = rounded(Psi0, "fp32")
+    psi = plan.new_states(Psi0)
+    eig = plan.rayleigh_ritz(psi)
+    theta, _, _, _ = oracle.rayleigh_ritz(Psi0, oracle.h_apply(Psi0, V, grid, box))
+    err = np.max(np.abs(eig - theta)) / np.max(np.abs(theta))
+    say("  eig err", err)
+    assert err < 2e-5
+    dup = plan.new_states(np.concatenate([Psi0[:m - 1], Psi0[:1]]))
+    from paper_0809_3739_amd import MpeError
+    with pytest.raises(MpeError):
+        plan.orthonormalize(dup)
+    p64 = P.Plan(grid, box, m, 2, "fp64")
+    with pytest.raises(MpeError):
+        p64.set_gemm_precision("fp32")
+
+
+def test_float32_gemms_solve_oscillator(P):
+    """The oscillator levels with float32 overlap GEMMs (float32 bar)."""
+    s = W.harmonic_system(32, 16.0, 10)
+    say("solve oscillator fp32 gemms")
+    plan = P.Plan(s.grid, s.box, 10, 4, "fp32")
+    plan.set_potential(s.V)
+    plan.set_gemm_precision("fp32")
+    psi = plan.new_states(W.random_states(1, 10, s.grid))
+    res = P.solve(plan, psi, dt0=0.1, gamma=1e-9)
+    exact = dense.separable_oscillator_levels(32, 16.0, 10)
+    err = np.max(np.abs(res.eig[:10] - exact) / np.abs(exact))
+    say("  eig rel err", err, "iterations", res.iterations)
+    assert err < 1e-6
+
+
 def test_iterate_lockstep_oscillator(P):
     """Config-1 geometry: 32^3 oscillator, 10 states, order 4, dt = 0.1, float64, lockstep."""
     s = W.harmonic_system(32, 16.0, 10)
