@@ -760,7 +760,7 @@ mpe_status mpe_plan_create(mpe_plan* out, const int32_t grid[3], const double bo
   long rch;
   const int nrch = rot_chunks(p, &rch);
   p->partials_bytes = std::max((size_t)3 * ngch * p->mp * p->mp, (size_t)nrch * p->mp) * sizeof(double);
-  p->rot_count = (size_t)p->mp * p->mp / 4 + 4;   // U of the Jacobi solver: mp x mp doubles
+  p->rot_count = small_dense_rot_doubles(p->max_sweeps) / 4 + 4;   // Jacobi rotation log
   p->res_bytes = 6 * MAXM * sizeof(double) + 4 * sizeof(int);
   const int tablen = p->nxh + p->ny + p->nz;
   std::vector<double> r;

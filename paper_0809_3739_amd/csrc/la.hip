@@ -324,6 +324,8 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   __shared__ double cs[MAXM / 2 + 1][2];
   __shared__ int pq[MAXM / 2 + 1][2];
   __shared__ double dg[MAXM];
+  constexpr int LOGCH = 20;                     // rotation-log steps staged at a time
+  __shared__ double lgbuf[LOGCH * SD_LOG_STRIDE];
   const int m = d.m, LD = d.mp + 1;
   const int tid = threadIdx.x;
   double* L = d.L;            // mp x mp, lower triangle
@@ -431,12 +433,9 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   for (int i = tid; i < m; i += SD_THREADS) dmax = fmax(dmax, fabs(A(i, i)));
   const double floor_abs = 32.0 * 2.220446049250313e-16 * fmax(block_max(dmax, red), 1e-300) / d.tol;
   const double rot_tol = 0.125 * d.tol;
-  // eigenvectors accumulate in U (global, L2 resident), stored by columns
-  // (Ut[c * mp + r] = U[r][c]) so that a rotation of columns p, q is two
-  // contiguous sweeps: U <- U J each step
-  double* Ut = d.rot;
-  for (int e = tid; e < m * m; e += SD_THREADS) Ut[(e / m) * (long)d.mp + e % m] = (e / m == e % m) ? 1.0 : 0.0;
-  __syncthreads();
+  // the rotations of every step are logged (flag, then (c, s) per pair) and the
+  // eigenvectors are rebuilt from the log once the sweeps are done
+  double* lg = d.rot;
   int sweep = 0;
   bool converged = false;
   int gstep = 0;
@@ -483,22 +482,12 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
         cs[k][1] = sn;
         pq[k][0] = p;
         pq[k][1] = q;
+        lg[(long)gstep * SD_LOG_STRIDE + 1 + 2 * k] = c;
+        lg[(long)gstep * SD_LOG_STRIDE + 2 + 2 * k] = sn;
       }
       __syncthreads();
+      if (tid == 0) lg[(long)gstep * SD_LOG_STRIDE] = step_active[cur] ? 1.0 : 0.0;
       if (step_active[cur]) {   // uniform
-        // columns p, q of U (neighbouring threads take neighbouring rows of one pair)
-        for (int e = tid; e < half * m; e += SD_THREADS) {
-          const int k = e / m, r = e - k * m;
-          const int pk = pq[k][0], qk = pq[k][1];
-          if (qk < m) {
-            const double ck = cs[k][0], sk = cs[k][1];
-            double* up_ = Ut + (long)pk * d.mp + r;
-            double* uq_ = Ut + (long)qk * d.mp + r;
-            const double up = *up_, uq = *uq_;
-            *up_ = ck * up - sk * uq;
-            *uq_ = sk * up + ck * uq;
-          }
-        }
         for (int e = tid; e < half * half; e += SD_THREADS) {
           const int k = e / half, l = e - k * half;
           const int pk = pq[k][0], qk = pq[k][1], pl = pq[l][0], ql = pq[l][1];
@@ -540,8 +529,56 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   }
   __threadfence_block();
   __syncthreads();
-  // U into LDS (A is no longer needed)
-  for (int e = tid; e < m * m; e += SD_THREADS) A(e % m, e / m) = Ut[(e / m) * (long)d.mp + e % m];
+  // ---- U = J_1 J_2 ... J_G rebuilt in LDS (A is no longer needed) from the log:
+  // row r of U is carried by the 8 consecutive lanes 8r..8r+7 of one wavefront,
+  // which split each step's (disjoint) pairs, so a step needs only an ordering
+  // point within the wavefront
+  for (int e = tid; e < m * m; e += SD_THREADS) A(e / m, e % m) = (e / m == e % m) ? 1.0 : 0.0;
+  __threadfence_block();
+  __syncthreads();
+  {
+    // the log is staged through LDS LOGCH steps at a time (one coalesced copy by
+    // the whole work-group), then replayed from there
+    const int r = tid >> 3, sub = tid & 7;
+    const int G = gstep;
+    for (int g0 = 0; g0 < G; g0 += LOGCH) {
+      const int cnt = min(LOGCH, G - g0);
+      for (int e = tid; e < cnt * SD_LOG_STRIDE; e += SD_THREADS) lgbuf[e] = lg[(long)g0 * SD_LOG_STRIDE + e];
+      __syncthreads();
+      if (r < m) {
+        double* ur = sh + r * LD;
+        for (int gg = 0; gg < cnt; ++gg) {
+          const double* lgs = lgbuf + gg * SD_LOG_STRIDE;
+          if (lgs[0] == 0.0) continue;   // same value for every lane
+          const int step = (g0 + gg) % (n - 1);
+          for (int k = sub; k < half; k += 8) {
+            // round-robin pairs without integer division (k < n/2, step < n-1)
+            int p, q;
+            if (k == 0) {
+              p = 0;
+              q = step + 1;
+            } else {
+              int a = k + step, b = n - 1 - k + step;
+              if (a >= n - 1) a -= n - 1;
+              if (b >= n - 1) b -= n - 1;
+              p = a + 1;
+              q = b + 1;
+            }
+            if (p > q) { const int t = p; p = q; q = t; }
+            if (q < m) {
+              const double c = lgs[1 + 2 * k], sn = lgs[2 + 2 * k];
+              const double up = ur[p], uq = ur[q];
+              ur[p] = c * up - sn * uq;
+              ur[q] = sn * up + c * uq;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      __syncthreads();   // before the next chunk overwrites lgbuf
+    }
+  }
   __syncthreads();
   stamp(d, 4);
   // C = L^-T U

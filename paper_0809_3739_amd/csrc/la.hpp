@@ -7,6 +7,11 @@ namespace mpe {
 constexpr int MAXM = 128;  // states (incl. guards) per system handled by one plan
 
 enum SmallDenseMode { SD_ORTHO = 0, SD_RR = 1 };
+
+// Jacobi rotation log of the small dense solve: per step a flag and (c, s) for
+// every pair; the rotation buffer (SmallDenseArgs::rot) holds max_sweeps sweeps.
+constexpr int SD_LOG_STRIDE = 1 + 2 * (MAXM / 2 + 1);
+inline size_t small_dense_rot_doubles(int max_sweeps) { return (size_t)max_sweeps * (MAXM + 1) * SD_LOG_STRIDE; }
 enum SmallDenseStatus { ST_OK = 0, ST_NOT_SPD = 1, ST_EIG_NO_CONV = 2, ST_NONFINITE = 3 };
 
 // partial[prod][chunk][mp][mp] = X_prod Y_prod^T over the chunk's points
@@ -23,7 +28,7 @@ struct SmallDenseArgs {
   const double* S;      // mp x mp overlap
   const double* Hs;     // mp x mp projected H (SD_RR)
   double* L;            // mp x mp workspace (Cholesky factor)
-  double* rot;          // mp x mp workspace: the Jacobi eigenvectors U
+  double* rot;          // workspace: the Jacobi rotation log (small_dense_rot_doubles(max_sweeps))
   double* scratch;      // >= 2*MAXM doubles
   double* C;            // out: mp x mp, Psi_j = sum_i C[i][j] Phi_i
   double* theta;        // out: m Ritz values ascending (SD_RR)

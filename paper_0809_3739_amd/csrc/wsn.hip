@@ -703,7 +703,8 @@ mpe_status wsn_create(wsn_net* out, int32_t grid, int32_t n_out, int32_t max_bat
        alloc((void**)&n->g_a1, B * v32 * 16 * 4);
   // loss scratch: gram partials (2 products x <= 128 chunks), M and S, B^T, G (then W), A, Sid, L, rot, U, Q,
   // theta, small-dense scratch, status, loss values
-  n->scratch_bytes = ((size_t)256 * 128 * 128 + 11 * 128 * 128 + 128 + 256 + 16 + 16) * sizeof(double);
+  n->scratch_bytes = ((size_t)256 * 128 * 128 + 11 * 128 * 128 + 128 + 256 + 16 + 16 +
+                      mpe::small_dense_rot_doubles(60)) * sizeof(double);
   ok = ok && alloc((void**)&n->scratch, n->scratch_bytes);
   if (!ok) {
     wsn_destroy(n);
@@ -908,6 +909,7 @@ mpe_status wsn_procrustes_loss(wsn_net n, const float* y, const float* target, i
   double* sds = theta + 128;
   int* status = reinterpret_cast<int*>(sds + 256);
   double* lv = sds + 256 + 16;     // [||y||^2, loss, nuclear norm]
+  double* jlog = lv + 16;          // Jacobi rotation log
   mpe::GramArgs g;
   std::memset(&g, 0, sizeof(g));
   g.X[0] = y;
@@ -933,7 +935,7 @@ mpe_status wsn_procrustes_loss(wsn_net n, const float* y, const float* target, i
   d.S = Sid;
   d.Hs = A;
   d.L = Lb;
-  d.rot = rot;
+  d.rot = jlog;
   d.scratch = sds;
   d.C = U;
   d.theta = theta;
