@@ -467,9 +467,11 @@ int rot_chunks(mpe_plan p, long* chunk) {
 }
 
 // Overlaps X_i Y_i^T (i < nprod) reduced into outs[i] (mp x mp float64 each, contiguous from out0).
-mpe_status run_gram(mpe_plan p, const void* const* X, const void* const* Y, int nprod, double* out0) {
+mpe_status run_gram(mpe_plan p, const void* const* X, const void* const* Y, int nprod, double* out0,
+                    int upper_mask = 0) {
   GramArgs g;
   std::memset(&g, 0, sizeof(g));
+  g.upper_mask = upper_mask;
   for (int i = 0; i < nprod; ++i) {
     g.X[i] = X[i];
     g.Y[i] = Y[i];
@@ -597,7 +599,7 @@ mpe_status enqueue_iterate(mpe_plan p, void* psi) {
   if (s == MPE_OK) s = run_h(p, p->phi, p->hphi);
   const void* X[3] = {p->phi, p->phi, psi};
   const void* Y[3] = {p->phi, p->hphi, p->phi};
-  if (s == MPE_OK) s = run_gram(p, X, Y, 3, p->S());   // S, Hs, M contiguous
+  if (s == MPE_OK) s = run_gram(p, X, Y, 3, p->S(), 2);   // S, Hs (upper tiles), M contiguous
   if (s == MPE_OK) {
     hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, p->re(), p->reperp(), p->st);
     if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));
@@ -893,7 +895,7 @@ mpe_status mpe_rayleigh_ritz(mpe_plan p, void* psi, double* eig) {
   mpe_status s = run_h(p, psi, p->hphi);
   const void* X[2] = {psi, psi};
   const void* Y[2] = {psi, p->hphi};
-  if (s == MPE_OK) s = run_gram(p, X, Y, 2, p->S());
+  if (s == MPE_OK) s = run_gram(p, X, Y, 2, p->S(), 2);   // Hs from its upper tiles
   if (s == MPE_OK) s = run_small_dense(p, SD_RR);
   if (s == MPE_OK) s = run_rotate(p, psi, p->hphi, psi, p->hphi);
   if (s != MPE_OK) return s;
@@ -1336,7 +1338,7 @@ mpe_status enqueue_batch_iterate(mpe_batch b, void* const* psi, hipStream_t st) 
     p->st = si;
     const void* X[3] = {p->phi, p->phi, psi[i]};
     const void* Y[3] = {p->phi, p->hphi, p->phi};
-    mpe_status s = run_gram(p, X, Y, 3, p->S());
+    mpe_status s = run_gram(p, X, Y, 3, p->S(), 2);
     if (s == MPE_OK) {
       hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, p->re(), p->reperp(), si);
       if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));

@@ -34,8 +34,10 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
 // ------------------------------------------------------------------ Gram partials
 // Work-group: 256 threads (4 waves).  The 16x16 output tiles of an mp x mp
 // product (NT = mp/16 per side, compile time) are dealt round-robin to the
-// waves; for X == Y (SYM) only tiles ti <= tj are formed and mirrored on
-// store.  Points are staged through LDS in slabs of GSLAB, transposed to
+// waves.  Modes: GRAM_FULL forms all tiles; GRAM_SELF (X == Y) and GRAM_UPPER
+// (X != Y, a product symmetric in exact arithmetic, such as Psi (H Psi)^T) form
+// only tiles ti <= tj and mirror them on store, GRAM_SELF staging one array.
+// Points are staged through LDS in slabs of GSLAB, transposed to
 // [point][state]; the next slab is loaded into registers while the MFMAs of
 // the current one run.
 constexpr int GSLAB = 32;
@@ -46,6 +48,11 @@ struct GramTiles {
   static constexpr int count = SYM ? NT * (NT + 1) / 2 : NT * NT;
   static constexpr int per_wave = (count + 3) / 4;
 };
+
+static int gram_mode(const GramArgs& g, int i) {
+  if (g.X[i] == g.Y[i]) return GRAM_SELF;
+  return (g.upper_mask >> i) & 1 ? GRAM_UPPER : GRAM_FULL;
+}
 
 __device__ __forceinline__ void tile_coords(int u, int nt, bool sym, int& ti, int& tj) {
   if (!sym) {
@@ -61,14 +68,15 @@ __device__ __forceinline__ void tile_coords(int u, int nt, bool sym, int& ti, in
   tj = ti + u;
 }
 
-template <typename F, int NT, bool SYM>
+template <typename F, int NT, int MODE>
 __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
+  constexpr bool ONE = MODE == GRAM_SELF, TRI = MODE != GRAM_FULL;
   constexpr int mp = NT * 16;
-  constexpr int TPW = GramTiles<NT, SYM>::per_wave;
-  constexpr int NTILE = GramTiles<NT, SYM>::count;
+  constexpr int TPW = GramTiles<NT, TRI>::per_wave;
+  constexpr int NTILE = GramTiles<NT, TRI>::count;
   constexpr int PER = (mp * GSLAB + 255) / 256;   // staged elements per thread and array
   __shared__ double xs[GSLAB][GLD];
-  __shared__ double ys[SYM ? 1 : GSLAB][SYM ? 1 : GLD];
+  __shared__ double ys[ONE ? 1 : GSLAB][ONE ? 1 : GLD];
   const int prod = blockIdx.y;
   const F* __restrict__ X = reinterpret_cast<const F*>(g.X[prod]);
   const F* __restrict__ Y = reinterpret_cast<const F*>(g.Y[prod]);
@@ -82,7 +90,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int u = wave + 4 * t;
-    tile_coords(u < NTILE ? u : 0, NT, SYM, tiv[t], tjv[t]);
+    tile_coords(u < NTILE ? u : 0, NT, TRI, tiv[t], tjv[t]);
   }
   d4 acc[TPW];
 #pragma unroll
@@ -97,7 +105,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
       const long p = p0 + q;
       const bool ok = e < mp * GSLAB && st < m && p < p_end;
       px[r] = ok ? X[(long)st * N + p] : F(0);
-      if (!SYM) py[r] = ok ? Y[(long)st * N + p] : F(0);
+      if (!ONE) py[r] = ok ? Y[(long)st * N + p] : F(0);
     }
   };
   auto stage = [&]() {
@@ -107,7 +115,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
       if (e < mp * GSLAB) {
         const int st = e / GSLAB, q = e - st * GSLAB;
         xs[q][st] = (double)px[r];
-        if (!SYM) ys[q][st] = (double)py[r];
+        if (!ONE) ys[q][st] = (double)py[r];
       }
     }
   };
@@ -123,7 +131,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
       for (int t = 0; t < TPW; ++t) {
         if (TPW * 4 == NTILE || wave + 4 * t < NTILE) {
           const double a = xs[kq][tiv[t] * 16 + (lane & 15)];
-          const double b = SYM ? xs[kq][tjv[t] * 16 + (lane & 15)] : ys[kq][tjv[t] * 16 + (lane & 15)];
+          const double b = ONE ? xs[kq][tjv[t] * 16 + (lane & 15)] : ys[kq][tjv[t] * 16 + (lane & 15)];
           acc[t] = mfma16(a, b, acc[t]);
         }
       }
@@ -138,7 +146,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int i = tiv[t] * 16 + drow(lane, r), j = tjv[t] * 16 + (lane & 15);
         out[(long)i * mp + j] = acc[t][r];
-        if (SYM && tiv[t] != tjv[t]) out[(long)j * mp + i] = acc[t][r];
+        if (TRI && tiv[t] != tjv[t]) out[(long)j * mp + i] = acc[t][r];
       }
     }
   }
@@ -148,15 +156,16 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
 // GEMMs): 512 threads (8 waves), points staged as float, v_mfma_f32_16x16x4f32
 // with float32 accumulation over one slab of GSLAB points, then added into
 // float64 per-tile sums (one rounding per 32 products), float64 partials out.
-template <int NT, bool SYM>
+template <int NT, int MODE>
 __global__ __launch_bounds__(512) void gram32_partial_kernel(GramArgs g) {
+  constexpr bool ONE = MODE == GRAM_SELF, TRI = MODE != GRAM_FULL;
   constexpr int W = 8;
   constexpr int mp = NT * 16;
-  constexpr int NTILE = GramTiles<NT, SYM>::count;
+  constexpr int NTILE = GramTiles<NT, TRI>::count;
   constexpr int TPW = (NTILE + W - 1) / W;
   constexpr int PER = (mp * GSLAB + 511) / 512;
   __shared__ float xs[GSLAB][GLD];
-  __shared__ float ys[SYM ? 1 : GSLAB][SYM ? 1 : GLD];
+  __shared__ float ys[ONE ? 1 : GSLAB][ONE ? 1 : GLD];
   const int prod = blockIdx.y;
   const float* __restrict__ X = reinterpret_cast<const float*>(g.X[prod]);
   const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y[prod]);
@@ -169,7 +178,7 @@ __global__ __launch_bounds__(512) void gram32_partial_kernel(GramArgs g) {
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int u = wave + W * t;
-    tile_coords(u < NTILE ? u : 0, NT, SYM, tiv[t], tjv[t]);
+    tile_coords(u < NTILE ? u : 0, NT, TRI, tiv[t], tjv[t]);
   }
   d4 sum[TPW];
 #pragma unroll
@@ -183,7 +192,7 @@ __global__ __launch_bounds__(512) void gram32_partial_kernel(GramArgs g) {
       const long p = p0 + q;
       const bool ok = e < mp * GSLAB && st < m && p < p_end;
       px[r] = ok ? X[(long)st * N + p] : 0.f;
-      if (!SYM) py[r] = ok ? Y[(long)st * N + p] : 0.f;
+      if (!ONE) py[r] = ok ? Y[(long)st * N + p] : 0.f;
     }
   };
   auto stage = [&]() {
@@ -193,7 +202,7 @@ __global__ __launch_bounds__(512) void gram32_partial_kernel(GramArgs g) {
       if (e < mp * GSLAB) {
         const int st = e / GSLAB, q = e - st * GSLAB;
         xs[q][st] = px[r];
-        if (!SYM) ys[q][st] = py[r];
+        if (!ONE) ys[q][st] = py[r];
       }
     }
   };
@@ -212,7 +221,7 @@ __global__ __launch_bounds__(512) void gram32_partial_kernel(GramArgs g) {
       for (int t = 0; t < TPW; ++t) {
         if (TPW * W == NTILE || wave + W * t < NTILE) {
           const float a = xs[kq][tiv[t] * 16 + (lane & 15)];
-          const float b = SYM ? xs[kq][tjv[t] * 16 + (lane & 15)] : ys[kq][tjv[t] * 16 + (lane & 15)];
+          const float b = ONE ? xs[kq][tjv[t] * 16 + (lane & 15)] : ys[kq][tjv[t] * 16 + (lane & 15)];
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
         }
       }
@@ -231,7 +240,7 @@ __global__ __launch_bounds__(512) void gram32_partial_kernel(GramArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int i = tiv[t] * 16 + 4 * (lane >> 4) + r, j = tjv[t] * 16 + (lane & 15);   // f32 D layout
         out[(long)i * mp + j] = sum[t][r];
-        if (SYM && tiv[t] != tjv[t]) out[(long)j * mp + i] = sum[t][r];
+        if (TRI && tiv[t] != tjv[t]) out[(long)j * mp + i] = sum[t][r];
       }
     }
   }
@@ -623,7 +632,12 @@ struct Mfma<float> {
 template <typename F, typename MT, bool WITH_H, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) == 4 ? 2 : 1))) void rotate_kernel(
     RotateArgs r) {
-  __shared__ MT cT[MAXM * MAXM];      // cT[j * mp + i] = C[i][j]
+  // C in LDS.  float32: row-major, rows padded by 16 words so that the two
+  // 16-lane row segments of one ds_read land in disjoint banks.  float64:
+  // transposed (cs[j * mp + i] = C[i][j]), measured faster for the 64-bit reads.
+  constexpr bool F32 = sizeof(MT) == 4;
+  constexpr int PAD = F32 ? 16 : 0;
+  __shared__ MT cs[MAXM * (MAXM + PAD)];
   __shared__ double thl[MAXM];
   __shared__ double rs[4][MAXM];
   if (r.status && r.status[0] != ST_OK) return;   // uniform: leave the states untouched
@@ -634,9 +648,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) 
   const int m = r.m;
   const long N = r.N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int LS = mp + PAD;
   for (int e = tid; e < mp * mp; e += 256) {
     const int i = e / mp, j = e - i * mp;
-    cT[j * mp + i] = (MT)r.C[e];
+    cs[F32 ? i * LS + j : j * mp + i] = (MT)r.C[e];
   }
   for (int j = tid; j < mp; j += 256) thl[j] = (WITH_H && j < m) ? r.theta[j] : 0.0;
   __syncthreads();
@@ -661,16 +676,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) 
     const bool pok = p < p_end;
     // B operands in groups of KG k-steps; the next group's loads are issued
     // before the current group's MFMAs so their latency hides behind them.
-    constexpr int KG = 2;
+    constexpr int KG = sizeof(MT) == 4 ? 4 : 2;
     MT b[KG], bh[KG], nb[KG], nbh[KG];
+    // float32: unconditional loads (masked lanes read element 0 and discard it),
+    // so no exec-mask branches surround them; the k-step offsets 4 k N are
+    // wave-uniform.  float64 keeps predicated loads (measured faster there).
+    const long lane_off = (long)(lane >> 4) * N + p;
     auto load_group = [&](int k0, MT (&x)[KG], MT (&xh)[KG]) {
 #pragma unroll
       for (int kk = 0; kk < KG; ++kk) {
         const int k = k0 + kk;
-        const int i = 4 * k + (lane >> 4);
-        const bool ok = k < nk && pok && i < m;
-        x[kk] = ok ? (MT)Phi[(long)i * N + p] : MT(0);
-        xh[kk] = (WITH_H && ok) ? (MT)HPhi[(long)i * N + p] : MT(0);
+        const bool ok = k < nk && pok && 4 * k + (lane >> 4) < m;
+        if constexpr (F32) {
+          const long idx = ok ? lane_off + (long)(4 * k) * N : 0;
+          const F v = Phi[idx];
+          x[kk] = ok ? (MT)v : MT(0);
+          if (WITH_H) {
+            const F vh = HPhi[idx];
+            xh[kk] = ok ? (MT)vh : MT(0);
+          } else {
+            xh[kk] = MT(0);
+          }
+        } else {
+          const long idx = lane_off + (long)(4 * k) * N;
+          x[kk] = ok ? (MT)Phi[idx] : MT(0);
+          xh[kk] = (WITH_H && ok) ? (MT)HPhi[idx] : MT(0);
+        }
       }
     };
     load_group(0, b, bh);
@@ -687,7 +718,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) 
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
             // A (16x4) = C^T tile: A[jj][kk] = C[4k + kk][t*16 + jj]
-            const MT a = cT[(t * 16 + (lane & 15)) * mp + 4 * k + (lane >> 4)];
+            const MT a = F32 ? cs[(4 * k + (lane >> 4)) * LS + t * 16 + (lane & 15)]
+                             : cs[(t * 16 + (lane & 15)) * mp + 4 * k + (lane >> 4)];
             ap[t] = M::mma(a, b[kk], ap[t]);
             if (WITH_H) ah[t] = M::mma(a, bh[kk], ah[t]);
           }
@@ -758,18 +790,18 @@ __global__ void variance_kernel(const double* S, const double* M, int m, int mp,
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename F, bool SYM>
+template <typename F, int MODE>
 static hipError_t launch_gram_t(const GramArgs& g, int nprod, int nchunks, hipStream_t st) {
   dim3 grid(nchunks, nprod), block(256);
   switch (g.mp / 16) {
-    case 1: hipLaunchKernelGGL((gram_partial_kernel<F, 1, SYM>), grid, block, 0, st, g); break;
-    case 2: hipLaunchKernelGGL((gram_partial_kernel<F, 2, SYM>), grid, block, 0, st, g); break;
-    case 3: hipLaunchKernelGGL((gram_partial_kernel<F, 3, SYM>), grid, block, 0, st, g); break;
-    case 4: hipLaunchKernelGGL((gram_partial_kernel<F, 4, SYM>), grid, block, 0, st, g); break;
-    case 5: hipLaunchKernelGGL((gram_partial_kernel<F, 5, SYM>), grid, block, 0, st, g); break;
-    case 6: hipLaunchKernelGGL((gram_partial_kernel<F, 6, SYM>), grid, block, 0, st, g); break;
-    case 7: hipLaunchKernelGGL((gram_partial_kernel<F, 7, SYM>), grid, block, 0, st, g); break;
-    case 8: hipLaunchKernelGGL((gram_partial_kernel<F, 8, SYM>), grid, block, 0, st, g); break;
+    case 1: hipLaunchKernelGGL((gram_partial_kernel<F, 1, MODE>), grid, block, 0, st, g); break;
+    case 2: hipLaunchKernelGGL((gram_partial_kernel<F, 2, MODE>), grid, block, 0, st, g); break;
+    case 3: hipLaunchKernelGGL((gram_partial_kernel<F, 3, MODE>), grid, block, 0, st, g); break;
+    case 4: hipLaunchKernelGGL((gram_partial_kernel<F, 4, MODE>), grid, block, 0, st, g); break;
+    case 5: hipLaunchKernelGGL((gram_partial_kernel<F, 5, MODE>), grid, block, 0, st, g); break;
+    case 6: hipLaunchKernelGGL((gram_partial_kernel<F, 6, MODE>), grid, block, 0, st, g); break;
+    case 7: hipLaunchKernelGGL((gram_partial_kernel<F, 7, MODE>), grid, block, 0, st, g); break;
+    case 8: hipLaunchKernelGGL((gram_partial_kernel<F, 8, MODE>), grid, block, 0, st, g); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -777,18 +809,18 @@ static hipError_t launch_gram_t(const GramArgs& g, int nprod, int nchunks, hipSt
 
 // Products with X == Y (overlaps of one block with itself) run as symmetric
 // launches; the others as general ones.  Partials land in g.partials[prod].
-template <bool SYM>
+template <int MODE>
 static hipError_t launch_gram32_t(const GramArgs& g, int nchunks, hipStream_t st) {
   dim3 grid(nchunks, 1), block(512);
   switch (g.mp / 16) {
-    case 1: hipLaunchKernelGGL((gram32_partial_kernel<1, SYM>), grid, block, 0, st, g); break;
-    case 2: hipLaunchKernelGGL((gram32_partial_kernel<2, SYM>), grid, block, 0, st, g); break;
-    case 3: hipLaunchKernelGGL((gram32_partial_kernel<3, SYM>), grid, block, 0, st, g); break;
-    case 4: hipLaunchKernelGGL((gram32_partial_kernel<4, SYM>), grid, block, 0, st, g); break;
-    case 5: hipLaunchKernelGGL((gram32_partial_kernel<5, SYM>), grid, block, 0, st, g); break;
-    case 6: hipLaunchKernelGGL((gram32_partial_kernel<6, SYM>), grid, block, 0, st, g); break;
-    case 7: hipLaunchKernelGGL((gram32_partial_kernel<7, SYM>), grid, block, 0, st, g); break;
-    case 8: hipLaunchKernelGGL((gram32_partial_kernel<8, SYM>), grid, block, 0, st, g); break;
+    case 1: hipLaunchKernelGGL((gram32_partial_kernel<1, MODE>), grid, block, 0, st, g); break;
+    case 2: hipLaunchKernelGGL((gram32_partial_kernel<2, MODE>), grid, block, 0, st, g); break;
+    case 3: hipLaunchKernelGGL((gram32_partial_kernel<3, MODE>), grid, block, 0, st, g); break;
+    case 4: hipLaunchKernelGGL((gram32_partial_kernel<4, MODE>), grid, block, 0, st, g); break;
+    case 5: hipLaunchKernelGGL((gram32_partial_kernel<5, MODE>), grid, block, 0, st, g); break;
+    case 6: hipLaunchKernelGGL((gram32_partial_kernel<6, MODE>), grid, block, 0, st, g); break;
+    case 7: hipLaunchKernelGGL((gram32_partial_kernel<7, MODE>), grid, block, 0, st, g); break;
+    case 8: hipLaunchKernelGGL((gram32_partial_kernel<8, MODE>), grid, block, 0, st, g); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -800,8 +832,10 @@ hipError_t launch_gram32(const GramArgs& g, int nprod, int nchunks, hipStream_t 
     one.X[0] = g.X[i];
     one.Y[0] = g.Y[i];
     one.partials = g.partials + (long)i * nchunks * g.mp * g.mp;
-    const hipError_t e = g.X[i] == g.Y[i] ? launch_gram32_t<true>(one, nchunks, st)
-                                          : launch_gram32_t<false>(one, nchunks, st);
+    const int mode = gram_mode(g, i);
+    const hipError_t e = mode == GRAM_SELF    ? launch_gram32_t<GRAM_SELF>(one, nchunks, st)
+                         : mode == GRAM_UPPER ? launch_gram32_t<GRAM_UPPER>(one, nchunks, st)
+                                              : launch_gram32_t<GRAM_FULL>(one, nchunks, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -813,10 +847,16 @@ hipError_t launch_gram(int is_double, const GramArgs& g, int nprod, int nchunks,
     one.X[0] = g.X[i];
     one.Y[0] = g.Y[i];
     one.partials = g.partials + (long)i * nchunks * g.mp * g.mp;
-    const bool sym = g.X[i] == g.Y[i];
+    const int mode = gram_mode(g, i);
     hipError_t e;
-    if (is_double) e = sym ? launch_gram_t<double, true>(one, 1, nchunks, st) : launch_gram_t<double, false>(one, 1, nchunks, st);
-    else e = sym ? launch_gram_t<float, true>(one, 1, nchunks, st) : launch_gram_t<float, false>(one, 1, nchunks, st);
+    if (is_double)
+      e = mode == GRAM_SELF    ? launch_gram_t<double, GRAM_SELF>(one, 1, nchunks, st)
+          : mode == GRAM_UPPER ? launch_gram_t<double, GRAM_UPPER>(one, 1, nchunks, st)
+                               : launch_gram_t<double, GRAM_FULL>(one, 1, nchunks, st);
+    else
+      e = mode == GRAM_SELF    ? launch_gram_t<float, GRAM_SELF>(one, 1, nchunks, st)
+          : mode == GRAM_UPPER ? launch_gram_t<float, GRAM_UPPER>(one, 1, nchunks, st)
+                               : launch_gram_t<float, GRAM_FULL>(one, 1, nchunks, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -15,9 +15,13 @@ inline size_t small_dense_rot_doubles(int max_sweeps) { return (size_t)max_sweep
 enum SmallDenseStatus { ST_OK = 0, ST_NOT_SPD = 1, ST_EIG_NO_CONV = 2, ST_NONFINITE = 3 };
 
 // partial[prod][chunk][mp][mp] = X_prod Y_prod^T over the chunk's points
+// Gram product modes (see gram_partial_kernel)
+enum { GRAM_FULL = 0, GRAM_SELF = 1, GRAM_UPPER = 2 };
+
 struct GramArgs {
   const void* X[3];
   const void* Y[3];
+  int upper_mask;       // bit i: product i is symmetric in exact arithmetic (upper tiles only)
   double* partials;
   long N;
   long chunk;
