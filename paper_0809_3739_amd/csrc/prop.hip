@@ -164,7 +164,23 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
   const bool packed = (g == 0 && h == 0);
   const int col = (g == 0) ? (h ? HALF : 0) : (h ? LX - g : g);   // LDS / spectrum column
   const int tyc = cact ? ty : 0;
-  auto cbuf = [&](int i) { return &lds[i * SROW + col]; };
+  // LDS slot of spectrum column c: the upper half of the columns is rotated by
+  // one slot (HALF -> LX - 1, c -> c - 1 above it).  The column phase pairs
+  // columns g and LX - g on neighbouring lanes; unrotated, g and LX - g share a
+  // bank for g = 0 mod 16 (and HALF shares one with 0), a two-way conflict in
+  // every pass of a column exchange.  Rotated, the columns of a half-wave fill
+  // distinct banks, and a row's TX consecutive columns stay in distinct ones.
+  static_assert(HALF % TX == 0, "row segments do not straddle the rotated half");
+  auto cslot = [&](int c) { return c < HALF ? c : (c == HALF ? LX - 1 : c - 1); };
+  // slot of column tx + TX m (m unrolled: only the segment holding HALF selects)
+  auto rslot = [&](int m) {
+    const int c = tx + TX * m;
+    if (TX * m < HALF) return c;
+    if (TX * m > HALF) return c - 1;
+    return tx == 0 ? LX - 1 : c - 1;
+  };
+  const int cs_col = cslot(col), cs_mirror = cslot(LX - col);
+  auto cbuf = [&](int i) { return &lds[i * SROW + cs_col]; };
   // Row-transform exchange slots: element i of row r at r * SROW + i + i / EX.
   // The exchange writes lane t's outputs at E t + k; one pad slot per E
   // elements moves the T lanes of a row to different LDS banks (without it
@@ -214,7 +230,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
     }
     if (cact) {
 #pragma unroll
-      for (int m = 0; m < EY; ++m) lds[(tyc + TY * m) * SROW + col] = v[m];
+      for (int m = 0; m < EY; ++m) lds[(tyc + TY * m) * SROW + cs_col] = v[m];
     }
     __syncthreads();
   };
@@ -237,7 +253,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
           const cx<F> z0 = r[0];
           v[m] = cx<F>{z0.x + z0.y, z0.x - z0.y};             // X0 + i X_LX (both real)
         } else {
-          const cx<F> A = r[col], B = conj(r[LX - col]);
+          const cx<F> A = r[cs_col], B = conj(r[cs_mirror]);
           const cx<F> E = scale(A + B, F(0.5));
           const cx<F> O = muli<-1>(scale(A - B, F(0.5)));
           v[m] = E + cmul(O, w);
@@ -344,7 +360,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
           fft<LX, -1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
           if (act) {
 #pragma unroll
-            for (int m = 0; m < EX; ++m) lds[row * SROW + tx + TX * m] = v[m];
+            for (int m = 0; m < EX; ++m) lds[row * SROW + rslot(m)] = v[m];
           }
         }
         if (more) {
@@ -366,7 +382,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
           cx<F> v[EX];
           if (act) {
 #pragma unroll
-            for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + tx + TX * m];
+            for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + rslot(m)];
           }
           fft<LX, +1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
           if (act) {
@@ -381,7 +397,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
           fft<LX, -1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
           if (act) {
 #pragma unroll
-            for (int m = 0; m < EX; ++m) lds[row * SROW + tx + TX * m] = v[m];
+            for (int m = 0; m < EX; ++m) lds[row * SROW + rslot(m)] = v[m];
           }
         }
       }
@@ -430,7 +446,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
         cx<F> v[EX];
         if (act) {
 #pragma unroll
-          for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + tx + TX * m];
+          for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + rslot(m)];
         }
         fft<LX, +1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
         if (act) {
@@ -479,7 +495,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
       cx<F> v[EX];
       if (act) {
 #pragma unroll
-        for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + tx + TX * m];
+        for (int m = 0; m < EX; ++m) v[m] = lds[row * SROW + rslot(m)];
       }
       fft<LX, +1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
       if (act) {
