@@ -149,8 +149,9 @@ mpe_status mpe_set_graph(mpe_plan p, int32_t on);
 int32_t mpe_last_jacobi_sweeps(mpe_plan p);
 
 /* Durations in microseconds of the phases of the last small dense solve
- * (Cholesky, triangular solves, Jacobi sweeps, eigenvector rebuild, back
- * substitution), from the GPU's constant clock; us must hold 5 doubles.
+ * (Cholesky, reduction to A = L^-1 Hs L^-T including L^-T, Jacobi sweeps,
+ * eigenvalue sort, eigenvector replay as seen by the first row group), from
+ * the GPU's constant clock; us must hold 5 doubles.
  * Diagnostic: synchronises the plan's stream. */
 mpe_status mpe_small_dense_phases(mpe_plan p, double* us);
 

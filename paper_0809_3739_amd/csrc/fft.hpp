@@ -166,8 +166,15 @@ struct Dft<16, DIR, F> {
     const F ws[8] = {F(0), s1, r2, c1, F(1), c1, r2, s1};
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      cx<F> w = cx<F>{wc[k], F(DIR) * ws[k]};
-      cx<F> t = cmul(o[k], w);
+      // W^0 = 1 and W^4 = DIR i exactly (a general product would multiply by 0)
+      cx<F> t;
+      if (k == 0) {
+        t = o[0];
+      } else if (k == 4) {
+        t = muli<DIR>(o[4]);
+      } else {
+        t = cmul(o[k], cx<F>{wc[k], F(DIR) * ws[k]});
+      }
       a[k] = e[k] + t;
       a[k + 8] = e[k] - t;
     }

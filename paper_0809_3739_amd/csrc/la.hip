@@ -7,7 +7,9 @@
 //    (v_mfma_f64_16x16x4f64); inputs of either precision are widened exactly.
 //  * reduce_kernel       : fixed-order float64 sum of chunk partials.
 //  * small_dense_kernel  : one work-group; S = L L^T, A = L^-1 Hs L^-T,
-//    cyclic parallel Jacobi on A, C = L^-T U with columns sorted by eigenvalue.
+//    cyclic parallel Jacobi on A (rotations logged), eigenvalues sorted, L^-T.
+//  * sd_replay_kernel    : C = L^-T U, the logged rotations applied to the rows
+//    of L^-T (one wavefront per row), columns sorted by eigenvalue.
 //  * rotate_kernel       : Psi = Phi C and (H Phi) C on float64 MFMA with the
 //    residual sum_p ((H Psi)_j - theta_j Psi_j)^2 accumulated in the epilogue.
 #include <hip/hip_runtime.h>
@@ -258,8 +260,9 @@ __global__ void reduce_kernel(const double* __restrict__ in, int nparts, long co
 }
 
 // ------------------------------------------------------------------ small dense problem
-// One work-group of 1024 threads.  LDS holds one mp x (mp+1) float64 matrix;
-// L, the Jacobi rotation log and scratch live in global memory (L2 resident).
+// One work-group of 1024 threads.  LDS holds one mp x (mp+1) float64 matrix
+// (S, then L, then A); W = L^-T, the product Hs W, the Jacobi rotation log and
+// scratch live in global memory (L2 resident).
 constexpr int SD_THREADS = 1024;
 
 __device__ __forceinline__ double block_max(double v, double* red) {
@@ -283,47 +286,31 @@ __device__ __forceinline__ void stamp(const SmallDenseArgs& d, int i) {
   if (d.ticks && threadIdx.x == 0) d.ticks[i] = (long long)__builtin_amdgcn_s_memrealtime();
 }
 
-// Triangular solves on the LDS matrix sh (row stride LD) with the Cholesky
-// factor L (global, row stride mp, lower).  Right-looking: one barrier per
-// pivot, all right-hand sides in parallel; rows are scaled by 1/L_ii at the end.
-//   ROWS = true : sh <- L^-1 sh      (forward, columns are right-hand sides)
-//   ROWS = false: sh <- sh L^-T      (forward, rows are right-hand sides)
-template <bool ROWS>
-__device__ void lower_solve(double* sh, int LD, const double* __restrict__ L, int mp, int m) {
-  for (int k = 0; k < m; ++k) {
-    const double inv = 1.0 / L[(long)k * mp + k];
-    const int rem = m - k - 1;
-    for (int e = threadIdx.x; e < rem * m; e += SD_THREADS) {
-      const int i = k + 1 + e / m, j = e % m;
-      const double lik = L[(long)i * mp + k];
-      if (ROWS) sh[i * LD + j] -= lik * (sh[k * LD + j] * inv);
-      else sh[j * LD + i] -= lik * (sh[j * LD + k] * inv);
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < m * m; e += SD_THREADS) {
-    const int i = e / m, j = e % m;
-    if (ROWS) sh[i * LD + j] /= L[(long)i * mp + i];
-    else sh[j * LD + i] /= L[(long)i * mp + i];
-  }
-  __syncthreads();
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __hiloint2double(hi, lo);
 }
 
-// sh <- L^-T sh (backward, columns are right-hand sides)
-__device__ void upper_solve_rows(double* sh, int LD, const double* __restrict__ L, int mp, int m) {
-  for (int k = m - 1; k >= 0; --k) {
-    const double inv = 1.0 / L[(long)k * mp + k];
-    for (int e = threadIdx.x; e < k * m; e += SD_THREADS) {
-      const int i = e / m, j = e % m;
-      sh[i * LD + j] -= L[(long)k * mp + i] * (sh[k * LD + j] * inv);
+// out(i, j, sum_k P(i, k) Q(k, j)) for i, j, k < mp (mp a multiple of 16), float64
+// MFMA, the 16x16 output tiles dealt round-robin to the work-group's wavefronts;
+// P and Q are read through the accessors (entries beyond the matrices are zero).
+template <typename PA, typename QA, typename OUT>
+__device__ void mfma_product(int mp, PA P, QA Q, OUT out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nt = mp / 16;
+  for (int t = wv; t < nt * nt; t += SD_THREADS / 64) {
+    const int i0 = (t / nt) * 16, j0 = (t % nt) * 16;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+    for (int k0 = 0; k0 < mp; k0 += 4) {
+      const double a = P(i0 + (lane & 15), k0 + (lane >> 4));
+      const double b = Q(k0 + (lane >> 4), j0 + (lane & 15));
+      acc = mfma16(a, b, acc);
     }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out(i0 + drow(lane, r), j0 + (lane & 15), acc[r]);
   }
-  for (int e = threadIdx.x; e < m * m; e += SD_THREADS) {
-    const int i = e / m, j = e % m;
-    sh[i * LD + j] /= L[(long)i * mp + i];
-  }
-  __syncthreads();
 }
 
 __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs d) {
@@ -333,11 +320,9 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   __shared__ double cs[MAXM / 2 + 1][2];
   __shared__ int pq[MAXM / 2 + 1][2];
   __shared__ double dg[MAXM];
-  constexpr int LOGCH = 20;                     // rotation-log steps staged at a time
-  __shared__ double lgbuf[LOGCH * SD_LOG_STRIDE];
   const int m = d.m, LD = d.mp + 1;
   const int tid = threadIdx.x;
-  double* L = d.L;            // mp x mp, lower triangle
+  double* L = d.L;            // mp x mp global workspace (the product Hs W)
   auto A = [&](int i, int j) -> double& { return sh[i * LD + j]; };
 
   if (tid == 0) flag = -1;
@@ -375,42 +360,51 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
     }
     return;
   }
-  for (int e = tid; e < m * m; e += SD_THREADS) {
-    const int i = e / m, j = e % m;
-    L[(long)i * d.mp + j] = j <= i ? A(i, j) : 0.0;
-  }
-  __threadfence_block();
-  __syncthreads();
-
   stamp(d, 1);
-  if (d.mode == SD_ORTHO) {
-    // C = L^-T: backward solve on the identity
-    for (int e = tid; e < m * m; e += SD_THREADS) A(e / m, e % m) = (e / m == e % m) ? 1.0 : 0.0;
-    __syncthreads();
-    upper_solve_rows(sh, LD, L, d.mp, m);
-    for (int e = tid; e < d.mp * d.mp; e += SD_THREADS) {
-      const int i = e / d.mp, j = e % d.mp;
-      d.C[e] = (i < m && j < m) ? A(i, j) : 0.0;
+  // ---- W = L^-T into C (the whole output for SD_ORTHO; for SD_RR the replay
+  // kernel turns it into C = W U).  One column per wavefront at a time, from L
+  // in LDS: column j solves L^T w = e_j backwards, lane l carries rows l and
+  // l + 64; the pivot being eliminated is read from its lane with readlane.
+  for (int i = tid; i < m; i += SD_THREADS) dg[i] = 1.0 / A(i, i);   // reciprocal pivots
+  __syncthreads();
+  {
+    const int wv = tid >> 6, ln = tid & 63;
+    for (int j = wv; j < d.mp; j += SD_THREADS / 64) {
+      double b0 = ln == j ? 1.0 : 0.0, b1 = ln + 64 == j ? 1.0 : 0.0;
+      if (j < m) {
+        for (int k = j; k >= 0; --k) {
+          const double wk = readlane_d(k < 64 ? b0 : b1, k & 63) * dg[k];
+          if (ln == k) b0 = wk;
+          if (ln + 64 == k) b1 = wk;
+          if (ln < k) b0 -= A(k, ln) * wk;
+          if (ln + 64 < k) b1 -= A(k, ln + 64) * wk;
+        }
+      }
+      if (ln < d.mp) d.C[(long)ln * d.mp + j] = (ln < m && ln <= j && j < m) ? b0 : 0.0;
+      if (ln + 64 < d.mp) d.C[(long)(ln + 64) * d.mp + j] = (ln + 64 < m && ln + 64 <= j && j < m) ? b1 : 0.0;
     }
+  }
+  if (d.mode == SD_ORTHO) {
     if (tid == 0) d.status[0] = ST_OK, d.status[1] = 0;
     return;
   }
+  __threadfence();   // W visible to every wavefront of the work-group
+  __syncthreads();
 
-  // ---- X = L^-1 Hs (column per thread), then A = L^-1 X^T (row per thread, in place)
-  for (int e = tid; e < m * m; e += SD_THREADS) A(e / m, e % m) = d.Hs[(e / m) * (long)d.mp + e % m];
+  // ---- A = W^T Hs W on float64 MFMA from L2-resident operands: Y = Hs W into
+  // the (no longer needed) global L, then A = W^T Y into LDS
+  mfma_product(d.mp, [&](int i, int k) { return (i < m && k < m) ? d.Hs[(long)i * d.mp + k] : 0.0; },
+               [&](int k, int j) { return d.C[(long)k * d.mp + j]; },
+               [&](int i, int j, double v) { L[(long)i * d.mp + j] = v; });
+  __threadfence();
   __syncthreads();
-  for (int e = tid; e < m * m; e += SD_THREADS) {   // symmetrise Hs
-    const int i = e / m, j = e % m;
-    if (i < j) {
-      const double v = 0.5 * (A(i, j) + A(j, i));
-      A(i, j) = v;
-      A(j, i) = v;
-    }
-  }
+  mfma_product(d.mp, [&](int i, int k) { return d.C[(long)k * d.mp + i]; },
+               [&](int k, int j) { return L[(long)k * d.mp + j]; },
+               [&](int i, int j, double v) {
+                 if (i < m && j < m) A(i, j) = v;
+               });
   __syncthreads();
-  lower_solve<true>(sh, LD, L, d.mp, m);    // X = L^-1 Hs
-  lower_solve<false>(sh, LD, L, d.mp, m);   // A = X L^-T
-  for (int e = tid; e < m * m; e += SD_THREADS) {
+  for (int e = tid; e < m * m; e += SD_THREADS) {   // symmetrise (Hs is symmetric up to rounding)
     const int i = e / m, j = e % m;
     if (i < j) {
       const double v = 0.5 * (A(i, j) + A(j, i));
@@ -538,68 +532,97 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   }
   __threadfence_block();
   __syncthreads();
-  // ---- U = J_1 J_2 ... J_G rebuilt in LDS (A is no longer needed) from the log:
-  // row r of U is carried by the 8 consecutive lanes 8r..8r+7 of one wavefront,
-  // which split each step's (disjoint) pairs, so a step needs only an ordering
-  // point within the wavefront
-  for (int e = tid; e < m * m; e += SD_THREADS) A(e / m, e % m) = (e / m == e % m) ? 1.0 : 0.0;
-  __threadfence_block();
-  __syncthreads();
-  {
-    // the log is staged through LDS LOGCH steps at a time (one coalesced copy by
-    // the whole work-group), then replayed from there
-    const int r = tid >> 3, sub = tid & 7;
-    const int G = gstep;
-    for (int g0 = 0; g0 < G; g0 += LOGCH) {
-      const int cnt = min(LOGCH, G - g0);
-      for (int e = tid; e < cnt * SD_LOG_STRIDE; e += SD_THREADS) lgbuf[e] = lg[(long)g0 * SD_LOG_STRIDE + e];
-      __syncthreads();
-      if (r < m) {
-        double* ur = sh + r * LD;
-        for (int gg = 0; gg < cnt; ++gg) {
-          const double* lgs = lgbuf + gg * SD_LOG_STRIDE;
-          if (lgs[0] == 0.0) continue;   // same value for every lane
-          const int step = (g0 + gg) % (n - 1);
-          for (int k = sub; k < half; k += 8) {
-            // round-robin pairs without integer division (k < n/2, step < n-1)
-            int p, q;
-            if (k == 0) {
-              p = 0;
-              q = step + 1;
-            } else {
-              int a = k + step, b = n - 1 - k + step;
-              if (a >= n - 1) a -= n - 1;
-              if (b >= n - 1) b -= n - 1;
-              p = a + 1;
-              q = b + 1;
-            }
-            if (p > q) { const int t = p; p = q; q = t; }
-            if (q < m) {
-              const double c = lgs[1 + 2 * k], sn = lgs[2 + 2 * k];
-              const double up = ur[p], uq = ur[q];
-              ur[p] = c * up - sn * uq;
-              ur[q] = sn * up + c * uq;
-            }
-          }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-        }
+  // C = W U with U = J_1 J_2 ... J_G: the replay kernel applies the logged
+  // rotations to the rows of W (already in C)
+  if (tid == 0) d.status[0] = ST_OK, d.status[1] = sweep;
+  stamp(d, 4);
+}
+
+// Eigenvector replay: row r of C (holding W = L^-T) becomes W_r J_1 J_2 ... J_G
+// with the Jacobi rotations of the log, columns then permuted to ascending
+// Ritz values.  Rows are independent: one wavefront per row, 4 rows per
+// work-group; the log is staged through LDS in chunks shared by the 4 rows.
+// Lane l carries row elements l and l + 64; in step s of the round-robin
+// ordering it needs the partner element of each and the pair index k that
+// holds the (c, s) of that pair in the log.
+constexpr int RP_ROWS = 4, RP_CHUNK = 24;
+
+__device__ __forceinline__ void rr_partner(int e, int step, int n, int half, int& k, int& f) {
+  if (e == 0) {           // pair 0 is (0, step + 1)
+    k = 0;
+    f = step + 1;
+    return;
+  }
+  int a = e - 1 - step;   // pair k (k > 0) is (1 + (k + step) mod (n-1), 1 + (n-1-k+step) mod (n-1))
+  if (a < 0) a += n - 1;
+  if (a == 0) {
+    k = 0;
+    f = 0;
+  } else if (a < half) {
+    k = a;
+    int b = n - 1 - k + step;
+    if (b >= n - 1) b -= n - 1;
+    f = b + 1;
+  } else {
+    k = n - 1 - a;
+    int b = k + step;
+    if (b >= n - 1) b -= n - 1;
+    f = b + 1;
+  }
+}
+
+__global__ __launch_bounds__(64 * RP_ROWS) void sd_replay_kernel(SmallDenseArgs d) {
+  __shared__ double lgbuf[RP_CHUNK * SD_LOG_STRIDE];
+  __shared__ double rowv[RP_ROWS][MAXM];
+  if (d.status[0] != ST_OK) return;   // uniform
+  const int m = d.m, mp = d.mp, n = (m + 1) & ~1, half = n / 2;
+  const int G = d.status[1] * (n - 1);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r = blockIdx.x * RP_ROWS + w;
+  const bool act = r < m;
+  double* ur = rowv[w];
+  const int e0 = lane, e1 = lane + 64;
+  const bool h0 = e0 < n, h1 = e1 < n;
+  double u0 = (act && e0 < m) ? d.C[(long)r * mp + e0] : 0.0;
+  double u1 = (act && e1 < m) ? d.C[(long)r * mp + e1] : 0.0;
+  if (h0) ur[e0] = u0;
+  if (h1) ur[e1] = u1;
+  int step = 0;
+  for (int g0 = 0; g0 < G; g0 += RP_CHUNK) {
+    const int cnt = min(RP_CHUNK, G - g0);
+    __syncthreads();   // the previous chunk is consumed
+    for (int e = tid; e < cnt * SD_LOG_STRIDE; e += 64 * RP_ROWS) lgbuf[e] = d.rot[(long)g0 * SD_LOG_STRIDE + e];
+    __syncthreads();
+    for (int gg = 0; gg < cnt; ++gg) {
+      const double* lgs = lgbuf + gg * SD_LOG_STRIDE;
+      if (lgs[0] != 0.0) {   // same value for every lane
+        int k0 = 0, f0 = 0, k1 = 0, f1 = 0;
+        if (h0) rr_partner(e0, step, n, half, k0, f0);
+        if (h1) rr_partner(e1, step, n, half, k1, f1);
+        const double v0 = h0 ? ur[f0] : 0.0, v1 = h1 ? ur[f1] : 0.0;
+        const double c0 = lgs[1 + 2 * k0], s0 = lgs[2 + 2 * k0];
+        const double c1 = lgs[1 + 2 * k1], s1 = lgs[2 + 2 * k1];
+        // pair (p, q), p < q: u_p <- c u_p - s u_q, u_q <- s u_p + c u_q
+        u0 = e0 < f0 ? c0 * u0 - s0 * v0 : s0 * v0 + c0 * u0;
+        u1 = e1 < f1 ? c1 * u1 - s1 * v1 : s1 * v1 + c1 * u1;
+        // every lane has read its partners before any lane writes (in-order LDS
+        // within the wavefront; the fence keeps the compiler from reordering)
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (h0) ur[e0] = u0;
+        if (h1) ur[e1] = u1;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
       }
-      __syncthreads();   // before the next chunk overwrites lgbuf
+      if (++step == n - 1) step = 0;
     }
   }
-  __syncthreads();
-  stamp(d, 4);
-  // C = L^-T U
-  upper_solve_rows(sh, LD, L, d.mp, m);
-  for (int e = tid; e < d.mp * d.mp; e += SD_THREADS) d.C[e] = 0.0;
-  __syncthreads();
-  for (int e = tid; e < m * m; e += SD_THREADS) {
-    const int i = e / m, j = e % m;
-    d.C[(long)i * d.mp + rank[j]] = A(i, j);
+  if (act) {
+    const int* rank = reinterpret_cast<const int*>(d.scratch + MAXM);
+    if (e0 < m) d.C[(long)r * mp + rank[e0]] = u0;
+    if (e1 < m) d.C[(long)r * mp + rank[e1]] = u1;
   }
-  if (tid == 0) d.status[0] = ST_OK, d.status[1] = sweep;
-  stamp(d, 5);
+  if (blockIdx.x == 0) stamp(d, 5);
 }
 
 // ------------------------------------------------------------------ rotation + residual epilogue
@@ -876,6 +899,9 @@ hipError_t prepare_small_dense() {
 hipError_t launch_small_dense(const SmallDenseArgs& d, hipStream_t st) {
   const size_t lds = (size_t)d.mp * (d.mp + 1) * sizeof(double);
   hipLaunchKernelGGL(small_dense_kernel, dim3(1), dim3(SD_THREADS), lds, st, d);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || d.mode != SD_RR) return e;
+  hipLaunchKernelGGL(sd_replay_kernel, dim3((d.m + RP_ROWS - 1) / RP_ROWS), dim3(64 * RP_ROWS), 0, st, d);
   return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ struct GramArgs {
 struct SmallDenseArgs {
   const double* S;      // mp x mp overlap
   const double* Hs;     // mp x mp projected H (SD_RR)
-  double* L;            // mp x mp workspace (Cholesky factor)
+  double* L;            // mp x mp workspace (holds Hs L^-T during SD_RR)
   double* rot;          // workspace: the Jacobi rotation log (small_dense_rot_doubles(max_sweeps))
   double* scratch;      // >= 2*MAXM doubles
   double* C;            // out: mp x mp, Psi_j = sum_i C[i][j] Phi_i

@@ -126,7 +126,7 @@ class Plan:
     def small_dense_phases(self) -> dict:
         us = np.zeros(5)
         self._check(self.lib.mpe_small_dense_phases(self.h, _dptr(us)))
-        return dict(zip(("cholesky", "tri_solves", "jacobi", "rebuild", "back_subst"), us.tolist()))
+        return dict(zip(("cholesky", "reduction", "jacobi", "sort", "replay"), us.tolist()))
 
     @property
     def last_jacobi_sweeps(self) -> int:
