@@ -439,6 +439,16 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   // the rotations of every step are logged (flag, then (c, s) per pair) and the
   // eigenvectors are rebuilt from the log once the sweeps are done
   double* lg = d.rot;
+  // the 2x2 blocks (k, l) of this thread, fixed for every step (k = e / half, l = e % half)
+  constexpr int SD_BLOCKS = (MAXM / 2) * (MAXM / 2) / SD_THREADS;
+  int blk_k[SD_BLOCKS], blk_l[SD_BLOCKS], nblk = 0;
+#pragma unroll
+  for (int b = 0; b < SD_BLOCKS; ++b) {
+    const int e = tid + b * SD_THREADS;
+    blk_k[b] = e < half * half ? e / half : 0;
+    blk_l[b] = e < half * half ? e % half : 0;
+    if (e < half * half) nblk = b + 1;
+  }
   int sweep = 0;
   bool converged = false;
   int gstep = 0;
@@ -491,10 +501,13 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
       __syncthreads();
       if (tid == 0) lg[(long)gstep * SD_LOG_STRIDE] = step_active[cur] ? 1.0 : 0.0;
       if (step_active[cur]) {   // uniform
-        for (int e = tid; e < half * half; e += SD_THREADS) {
-          const int k = e / half, l = e - k * half;
-          const int pk = pq[k][0], qk = pq[k][1], pl = pq[l][0], ql = pq[l][1];
+#pragma unroll
+        for (int b = 0; b < SD_BLOCKS; ++b) {
+          if (b >= nblk) break;
+          const int k = blk_k[b], l = blk_l[b];
           const double ck = cs[k][0], sk = cs[k][1], cl = cs[l][0], sl = cs[l][1];
+          if (sk == 0.0 && sl == 0.0) continue;   // both rotations are the identity
+          const int pk = pq[k][0], qk = pq[k][1], pl = pq[l][0], ql = pq[l][1];
           const double b00 = A(pk, pl), b01 = A(pk, ql), b10 = A(qk, pl), b11 = A(qk, ql);
           // rows: J_k^T
           const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
