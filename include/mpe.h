@@ -155,6 +155,19 @@ int32_t mpe_last_jacobi_sweeps(mpe_plan p);
  * Diagnostic: synchronises the plan's stream. */
 mpe_status mpe_small_dense_phases(mpe_plan p, double* us);
 
+/* Selective propagation (Section III: only states whose variance has not
+ * reached the error bound need to be propagated).  The following mpe_iterate
+ * calls leave the first `locked` states of the block unpropagated: they enter
+ * the overlaps, the Rayleigh-Ritz rotation and the variances as Phi_j = Psi_j
+ * (so their R^E and R^E_perp come out as 0), while states locked..m-1 are
+ * propagated as usual and the whole block is orthonormalised and rotated.
+ * R^H is evaluated for every state.  0 <= locked <= m, else
+ * MPE_ERR_INVALID_ARGUMENT; 0 (the default) propagates every state.  Applies
+ * to mpe_iterate only (mpe_step always propagates the whole block). */
+mpe_status mpe_set_locked(mpe_plan p, int32_t locked);
+/* Current number of locked states (-1 for a null plan). */
+int32_t mpe_get_locked(mpe_plan p);
+
 /* Launch-shape knob: states per propagation launch (0 = all m). */
 mpe_status mpe_set_states_per_launch(mpe_plan p, int32_t states);
 

@@ -215,10 +215,16 @@ class IterResult:
 
 
 def iterate(psi: np.ndarray, V: np.ndarray, dt: float, K: int, grid, box,
-            hbar2_over_m: float = 1.0, keep_phi: bool = False) -> IterResult:
+            hbar2_over_m: float = 1.0, keep_phi: bool = False, locked: int = 0) -> IterResult:
     """One iteration: propagate (Eq. propstep with Eq. mcomp), orthonormalise (Eq. ortho),
-    Rayleigh-Ritz, and the variances R^E and R^H (Section III)."""
-    phi = mpe_apply(psi, V, dt, K, grid, box, hbar2_over_m)
+    Rayleigh-Ritz, and the variances R^E and R^H (Section III).
+
+    ``locked``: selective propagation (Section III, only states whose variance is
+    still above the bound are propagated): the first ``locked`` states are taken
+    over unpropagated, phi_j = psi_j, before the orthonormalisation."""
+    phi = np.array(psi, dtype=np.float64, copy=True)
+    if locked < len(psi):
+        phi[locked:] = mpe_apply(psi[locked:], V, dt, K, grid, box, hbar2_over_m)
     re, re_perp, _ = residual_e(psi, phi)
     Psi, _, _ = cholesky_orthonormalize(phi)
     HPsi = h_apply(Psi, V, grid, box, hbar2_over_m)

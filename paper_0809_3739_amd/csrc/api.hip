@@ -159,6 +159,7 @@ struct mpe_plan_s {
   double tab_dt = -1.0;
   double last_dt = -1.0;
   int states_per_launch = 0;
+  int locked = 0;                    // leading states mpe_iterate leaves unpropagated
   // launch shapes of the forward [0] and link [1] plane passes (PlaneArgs::persist_mode,
   // work-groups per CU); shape_ver counts changes so a captured graph can notice them
   int pmode[2] = {0, 0};
@@ -178,6 +179,7 @@ struct mpe_plan_s {
   hipGraphExec_t gexec = nullptr;
   const void* g_psi = nullptr;       // the graph bakes in this state block ...
   int g_spl = -1;                    // ... and this launch grouping
+  int g_locked = -1;                 // ... and this number of locked states
   int g_shape = -1;                  // ... and these plane-pass shapes
   hipEvent_t ev_in = nullptr;
   int64_t graph_launches = 0;
@@ -282,11 +284,11 @@ mpe_status ensure_tables(mpe_plan p, double dt) {
   return MPE_OK;
 }
 
-// Launch groups of states: [s0, s0 + count) with count <= states_per_launch.
+// Launch groups of states: [s0, s0 + count) covering [first, m) with count <= states_per_launch.
 template <typename Fn>
-hipError_t for_groups(mpe_plan p, Fn fn) {
+hipError_t for_groups(mpe_plan p, Fn fn, int first = 0) {
   const int G = (p->states_per_launch > 0 && p->states_per_launch < p->m) ? p->states_per_launch : p->m;
-  for (int s0 = 0; s0 < p->m; s0 += G) {
+  for (int s0 = first; s0 < p->m; s0 += G) {
     hipError_t e = fn(s0, std::min(G, p->m - s0));
     if (e != hipSuccess) return e;
   }
@@ -324,7 +326,9 @@ void* chain_spec(mpe_plan p, int k) {  // k = 0..K-1
 }
 
 // dst <- T_2K(dt) src, all m states (src may equal dst); tables for dt must be current.
-mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
+// Propagation of states [first, m) of src into dst (the rows below first are
+// not touched).
+mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0) {
   const size_t f = p->fsz;
   double c[MAX_K];
   mpe_coeffs(p->K, c);
@@ -345,7 +349,7 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
              a.persist_mode = p->pmode[0];
              a.persist_blocks = p->pbpc[0] * p->n_cu;
              return launch_plane(p->dbl, PM_FWD, p->nx, a, p->nz, cnt, p->st);
-           }));
+           }, first));
     toc(p, t);
     for (int l = 1; l <= k; ++l) {
       tic(p, t, MPE_KC_PENCIL);
@@ -353,7 +357,7 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
                PencilArgs a = pencil_base(p, Wk, ktab);
                a.state0 = s0;
                return launch_pencil(p->dbl, PK_EXP, p->nz, a, cnt, p->st);
-             }));
+             }, first));
       toc(p, t);
       if (l < k) {
         tic(p, t, MPE_KC_PLANE_LINK);
@@ -366,7 +370,7 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
                  a.persist_mode = p->pmode[1];
                  a.persist_blocks = p->pbpc[1] * p->n_cu;
                  return launch_plane(p->dbl, PM_LINK, p->nx, a, p->nz, cnt, p->st);
-               }));
+               }, first));
         toc(p, t);
       }
     }
@@ -385,9 +389,11 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
                a.real_out = out_k;
                a.state0 = s0;
                return launch_plane(p->dbl, PM_OUT, p->nx, a, p->nz, cnt, p->st);
-             }));
+             }, first));
     }
-    HIPCHK(p, launch_combine(p->dbl, p->tailbuf, (long)p->m * p->N, p->K, c, dst, (long)p->m * p->N, p->st));
+    const size_t off = (size_t)first * p->N * f;
+    HIPCHK(p, launch_combine(p->dbl, (const char*)p->tailbuf + off, (long)p->m * p->N, p->K, c, (char*)dst + off,
+                             (long)(p->m - first) * p->N, p->st));
   } else {
     HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
              PlaneArgs a = plane_base(p);
@@ -399,7 +405,7 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst) {
              for (int k = 0; k < p->K; ++k) a.coef[k] = c[k];
              a.state0 = s0;
              return launch_plane(p->dbl, PM_TAIL, p->nx, a, p->nz, cnt, p->st);
-           }));
+           }, first));
   }
   toc(p, t);
   return MPE_OK;
@@ -595,7 +601,10 @@ void host_roots(int L, std::vector<double>& out) {
 // Device work of one fused iteration on p->st, ending with the copy of the
 // results to the pinned mirror (no synchronisation).  Tables must be current.
 mpe_status enqueue_iterate(mpe_plan p, void* psi) {
-  mpe_status s = enqueue_step(p, psi, p->phi);
+  // locked states (Section III: only states not yet converged need propagating)
+  // enter the overlaps and the rotation unpropagated: Phi_j = Psi_j
+  if (p->locked > 0) HIPCHK(p, launch_copy16(p->phi, psi, (size_t)p->locked * p->N * p->fsz, p->st));
+  mpe_status s = enqueue_step(p, psi, p->phi, p->locked);
   if (s == MPE_OK) s = run_h(p, p->phi, p->hphi);
   const void* X[3] = {p->phi, p->phi, psi};
   const void* Y[3] = {p->phi, p->hphi, p->phi};
@@ -618,6 +627,7 @@ void drop_graph(mpe_plan p) {
   p->graph = nullptr;
   p->g_psi = nullptr;
   p->g_spl = -1;
+  p->g_locked = -1;
   p->g_shape = -1;
 }
 
@@ -642,6 +652,7 @@ mpe_status capture_iterate(mpe_plan p, void* psi) {
   HIPCHK(p, hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
   p->g_psi = psi;
   p->g_spl = p->states_per_launch;
+  p->g_locked = p->locked;
   p->g_shape = p->shape_ver;
   return MPE_OK;
 }
@@ -959,7 +970,8 @@ mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh
   if (s != MPE_OK) return s;
   p->last_dt = dt;
   if (p->use_graph && !p->prof) {
-    if (!p->gexec || p->g_psi != psi || p->g_spl != p->states_per_launch || p->g_shape != p->shape_ver) {
+    if (!p->gexec || p->g_psi != psi || p->g_spl != p->states_per_launch || p->g_shape != p->shape_ver ||
+        p->g_locked != p->locked) {
       s = capture_iterate(p, psi);
       if (s != MPE_OK) return s;
     }
@@ -998,6 +1010,15 @@ mpe_status mpe_set_graph(mpe_plan p, int32_t on) {
   if (!p->use_graph) drop_graph(p);
   return MPE_OK;
 }
+
+mpe_status mpe_set_locked(mpe_plan p, int32_t locked) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (locked < 0 || locked > p->m) return fail(p, MPE_ERR_INVALID_ARGUMENT, "locked must lie in [0, m]");
+  p->locked = locked;
+  return MPE_OK;
+}
+
+int32_t mpe_get_locked(mpe_plan p) { return p ? p->locked : -1; }
 
 mpe_status mpe_set_states_per_launch(mpe_plan p, int32_t states) {
   if (!p) return MPE_ERR_INVALID_ARGUMENT;

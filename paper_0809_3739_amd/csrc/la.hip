@@ -14,6 +14,7 @@
 //    residual sum_p ((H Psi)_j - theta_j Psi_j)^2 accumulated in the epilogue.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "la.hpp"
@@ -941,6 +942,21 @@ hipError_t launch_rotate(int is_double, bool with_h, const RotateArgs& r, int nc
                   : launch_rotate_t<double, double, false>(r, nchunks, st);
   return with_h ? launch_rotate_t<float, float, true>(r, nchunks, st)
                 : launch_rotate_t<float, float, false>(r, nchunks, st);
+}
+
+// dst <- src, n16 16-byte words (a plain kernel: usable inside captured graphs)
+__global__ void copy16_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src, long n16) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (long)gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes % 16) return hipErrorInvalidValue;
+  const long n16 = (long)(bytes / 16);
+  const long blocks = std::min<long>(8192, (n16 + 255) / 256);
+  hipLaunchKernelGGL(copy16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(dst),
+                     reinterpret_cast<const uint4*>(src), n16);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st) {

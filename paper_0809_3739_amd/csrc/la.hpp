@@ -65,6 +65,7 @@ hipError_t prepare_small_dense();
 hipError_t launch_small_dense(const SmallDenseArgs& d, hipStream_t st);
 hipError_t launch_rotate(int is_double, bool with_h, const RotateArgs& r, int nchunks, hipStream_t st);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
+hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st);
 hipError_t launch_variance(const double* S, const double* M, int m, int mp, double* re, double* re_perp, hipStream_t st);
 
 }  // namespace mpe

@@ -135,6 +135,15 @@ class Plan:
     def set_graph(self, on: bool):
         self._check(self.lib.mpe_set_graph(self.h, 1 if on else 0))
 
+    def set_locked(self, locked: int):
+        """Leave the first ``locked`` states unpropagated in the following
+        iterations (selective propagation; see mpe_set_locked)."""
+        self._check(self.lib.mpe_set_locked(self.h, int(locked)))
+
+    @property
+    def locked(self) -> int:
+        return int(self.lib.mpe_get_locked(self.h))
+
     def set_states_per_launch(self, states: int):
         self._check(self.lib.mpe_set_states_per_launch(self.h, int(states)))
 
@@ -266,12 +275,14 @@ class SolveResult:
     history: list = field(default_factory=list)
     stalled: bool = False
     stages: list = field(default_factory=list)
+    propagations: int = 0     # state propagations performed (fewer than iterations * m with locking)
 
 
 def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, reduce: float = 0.5,
           n_check: int | None = None, margin: float = 0.01, max_iter_per_level: int = 2000,
           max_levels: int = 30, orthonormalize_first: bool = True, callback=None,
-          stall_window: int | None = None, stall_gain: float = 0.02, accept=None) -> SolveResult:
+          stall_window: int | None = None, stall_gain: float = 0.02, accept=None,
+          lock_tol: float | None = None) -> SolveResult:
     """Iterate with the protocol of Section III until R^H_j < gamma for the
     first ``n_check`` states.
 
@@ -290,6 +301,15 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
     ``accept(out, iteration)``, if given, is called after every iteration; a
     non-None return {"eig", "rh"} ends the solve as converged with those values
     (an external, more accurate convergence check).
+
+    With ``lock_tol`` the solve propagates selectively (Section III: only
+    states whose variance is still above the bound need propagating): after
+    each iteration the leading run of states (ascending Ritz values, among the
+    first ``n_check``) with R^H_j <= lock_tol is left unpropagated in the next
+    iteration (``Plan.set_locked``).  R^H is evaluated for every state in every
+    iteration, so a locked state whose R^H rises again is released at once;
+    locks are dropped when dt changes, and a level only ends on an iteration
+    without locks, so its R^E test sees every state propagated.
     """
     n_check = plan.n_states if n_check is None else n_check
     t0 = time.perf_counter()
@@ -298,43 +318,63 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
     dt = dt0
     hist = []
     total = 0
+    props = 0
     out = None
-    for level in range(max_levels):
-        ge = margin * gamma * dt * dt
-        rh_level = []
-        for it in range(max_iter_per_level):
-            out = plan.iterate(psi, dt)
-            total += 1
-            rep = float(np.max(out["re_perp"][:n_check]))
-            rhm = float(np.max(out["rh"][:n_check]))
-            rh_level.append(rhm)
-            hist.append({"dt": dt, "it": total, "re_perp": rep, "rh": rhm, "eig0": float(out["eig"][0]),
-                         "t": time.perf_counter() - t0})
-            if callback:
-                callback(hist[-1])
-            if accept is not None:
-                ok = accept(out, total)
-                if ok is not None:
-                    return SolveResult(ok["eig"], ok["rh"], dt, total, level + 1, True, time.perf_counter() - t0,
-                                       hist)
-            if rhm < gamma:
-                break
-            if it > 0 and rep <= ge:
-                break
-            if stall_window and it >= stall_window:
-                before = min(rh_level[:-stall_window])
-                if min(rh_level[-stall_window:]) > (1.0 - stall_gain) * before:
-                    return SolveResult(out["eig"], out["rh"], dt, total, level + 1, False,
-                                       time.perf_counter() - t0, hist, stalled=True)
-        if float(np.max(out["rh"][:n_check])) < gamma:
-            return SolveResult(out["eig"], out["rh"], dt, total, level + 1, True, time.perf_counter() - t0, hist)
-        dt *= reduce
-    return SolveResult(out["eig"], out["rh"], dt, total, max_levels, False, time.perf_counter() - t0, hist)
+
+    def result(eig, rh, lev, conv, stalled=False):
+        r = SolveResult(eig, rh, dt, total, lev, conv, time.perf_counter() - t0, hist, stalled=stalled)
+        r.propagations = props
+        return r
+
+    plan.set_locked(0)
+    try:
+        for level in range(max_levels):
+            ge = margin * gamma * dt * dt
+            rh_level = []
+            plan.set_locked(0)
+            for it in range(max_iter_per_level):
+                locked = plan.locked
+                out = plan.iterate(psi, dt)
+                total += 1
+                props += plan.m - locked
+                rep = float(np.max(out["re_perp"][:n_check]))
+                rhm = float(np.max(out["rh"][:n_check]))
+                rh_level.append(rhm)
+                hist.append({"dt": dt, "it": total, "re_perp": rep, "rh": rhm, "eig0": float(out["eig"][0]),
+                             "locked": locked, "t": time.perf_counter() - t0})
+                if callback:
+                    callback(hist[-1])
+                if accept is not None:
+                    ok = accept(out, total)
+                    if ok is not None:
+                        return result(ok["eig"], ok["rh"], level + 1, True)
+                if rhm < gamma:
+                    break
+                if it > 0 and rep <= ge and locked == 0:
+                    break
+                if stall_window and it >= stall_window:
+                    before = min(rh_level[:-stall_window])
+                    if min(rh_level[-stall_window:]) > (1.0 - stall_gain) * before:
+                        return result(out["eig"], out["rh"], level + 1, False, stalled=True)
+                if lock_tol is not None:
+                    nl = 0
+                    rh = out["rh"]
+                    while nl < n_check and rh[nl] <= lock_tol:
+                        nl += 1
+                    if it > 0 and rep <= ge:
+                        nl = 0   # the level may be done: confirm with every state propagated
+                    plan.set_locked(nl)
+            if float(np.max(out["rh"][:n_check])) < gamma:
+                return result(out["eig"], out["rh"], level + 1, True)
+            dt *= reduce
+        return result(out["eig"], out["rh"], max_levels, False)
+    finally:
+        plan.set_locked(0)
 
 
 def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8,
                  stall_window: int = 20, check_below: float = 10.0, check_every: int = 10, callback=None,
-                 **kw) -> SolveResult:
+                 lock32: float | None = None, lock64: float | None = None, **kw) -> SolveResult:
     """Float32 iterations until converged, then float64 only if needed.
 
     Float32 arithmetic puts a floor under the R^H it measures (the transforms'
@@ -346,7 +386,9 @@ def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0
     gamma.  If float32 stalls first, float64 iterations continue from the
     converted states at the same dt until gamma.  The two plans must describe
     the same system; iterations and seconds of both stages are summed, and the
-    result's ``psi`` is the float64 block.
+    result's ``psi`` is the float64 block.  ``lock32`` and ``lock64`` are the
+    ``lock_tol`` of the two stages (selective propagation; None: every state
+    is propagated).
     """
     t0 = time.perf_counter()
     n_check = kw.get("n_check") or plan32.n_states
@@ -366,7 +408,7 @@ def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0
         return None
 
     r1 = solve(plan32, psi32, dt0=dt0, gamma=gamma, stall_window=stall_window, callback=callback, accept=accept,
-               **kw)
+               lock_tol=lock32, **kw)
     stages = [{"precision": "fp32", "iterations": r1.iterations, "seconds": round(r1.seconds, 3), "dt": r1.dt,
                "float64_checks": box.get("checks", 0), "max_rh": float(np.max(r1.rh[:n_check]))}]
     if r1.converged:
@@ -374,10 +416,11 @@ def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0
         r1.psi = box.get("psi")
         return r1
     psi64 = psi32.to(torch.float64)
-    r2 = solve(plan64, psi64, dt0=r1.dt, gamma=gamma, callback=callback, **kw)
+    r2 = solve(plan64, psi64, dt0=r1.dt, gamma=gamma, callback=callback, lock_tol=lock64, **kw)
     stages.append({"precision": "fp64", "iterations": r2.iterations, "seconds": round(r2.seconds, 3), "dt": r2.dt,
                    "max_rh": float(np.max(r2.rh[:n_check]))})
     r2.iterations += r1.iterations
+    r2.propagations += r1.propagations
     r2.levels += r1.levels - 1
     r2.seconds = time.perf_counter() - t0
     r2.history = r1.history + r2.history

@@ -403,6 +403,97 @@ def test_graph_replay_matches_eager(P):
             assert np.array_equal(x, y)
 
 
+LOCK_CASES = [((32, 32, 32), (12.0, 12.0, 12.0), 8, 8, "fp64", (0, 3, 8)),
+              ((128, 128, 8), (16.0, 16.0, 8.0), 4, 4, "fp64", (1,)),     # split tail (offset combine)
+              ((32, 32, 32), (12.0, 12.0, 12.0), 6, 6, "fp32", (2,))]
+
+
+@pytest.mark.parametrize("grid,box,m,order,prec,locks", LOCK_CASES, ids=[f"{c[0]}-{c[4]}" for c in LOCK_CASES])
+def test_locked_iterate_matches_oracle(P, grid, box, m, order, prec, locks):
+    """Selective propagation: mpe_iterate with the first `locked` states left
+    unpropagated against the oracle's iteration with the same lock."""
+    V = toy_potential(grid, box)
+    psi0 = W.random_states(31, m, grid)
+    ref0, _, _ = oracle.cholesky_orthonormalize(rounded(psi0, prec))
+    tol_e, tol_p = (1e-10, 1e-9) if prec == "fp64" else (2e-5, 2e-4)
+    for locked in locks:
+        say("locked iterate", grid, prec, "m", m, "order", order, "locked", locked)
+        plan = P.Plan(grid, box, m, order, prec)
+        plan.set_potential(V)
+        psi = plan.new_states(ref0)
+        plan.set_locked(locked)
+        assert plan.locked == locked
+        out = plan.iterate(psi, 0.3)
+        r = oracle.iterate(rounded(ref0, prec), V, 0.3, order // 2, grid, box, locked=locked)
+        e = np.max(np.abs(out["eig"] - r.theta) / np.abs(r.theta))
+        Pg = psi.cpu().numpy().astype(np.float64).reshape(m, -1)
+        Pr = r.psi.reshape(m, -1)
+        proj = np.linalg.norm(Pg.T @ (Pg @ Pr.T) - Pr.T) / math.sqrt(m)
+        say(f"  eig rel {e:.2e} proj {proj:.2e} re_perp locked max {np.max(out['re_perp'][:locked], initial=0):.1e}")
+        assert e < tol_e and proj < tol_p
+        if prec == "fp64":
+            assert np.max(np.abs(out["re_perp"][:locked]), initial=0.0) < 1e-13
+            np.testing.assert_allclose(out["re_perp"][locked:], r.re_perp[locked:], rtol=1e-6, atol=1e-14)
+            np.testing.assert_allclose(out["rh"], r.rh, rtol=1e-6, atol=1e-14)
+
+
+def test_locked_graph_replay_matches_eager(P):
+    """Changing the number of locked states between graph replays re-captures the
+    graph: replay and eager launches agree bitwise over a sequence of locks."""
+    grid, box = (32, 32, 32), (12.0, 12.0, 12.0)
+    say("locked graph replay vs eager")
+    V = toy_potential(grid, box)
+    psi0 = W.random_states(5, 8, grid)
+    runs = []
+    for graph in (False, True):
+        plan = P.Plan(grid, box, 8, 6, "fp64")
+        plan.set_potential(V)
+        plan.set_graph(graph)
+        psi = plan.new_states(psi0)
+        plan.orthonormalize(psi)
+        outs = []
+        for locked in (0, 2, 2, 5, 0, 8, 3):
+            plan.set_locked(locked)
+            r = plan.iterate(psi, 0.3)
+            outs.append((psi.cpu().numpy().copy(), r["eig"].copy(), r["rh"].copy(), r["re_perp"].copy()))
+        runs.append(outs)
+    for a, b in zip(runs[0], runs[1]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_locked_bounds(P):
+    grid, box = (16, 16, 16), (8.0, 8.0, 8.0)
+    say("locked bounds")
+    plan = P.Plan(grid, box, 4, 4, "fp64", n_guard=1)
+    for bad in (-1, 6):
+        with pytest.raises(P.MpeError):
+            plan.set_locked(bad)
+    plan.set_locked(5)
+    assert plan.locked == 5
+
+
+def test_solve_with_locking_oscillator(P):
+    """The driver's selective propagation reaches the exact oscillator levels with
+    fewer state propagations than the unlocked solve."""
+    s = W.harmonic_system(32, 16.0, 10)
+    exact = dense.separable_oscillator_levels(32, 16.0, 10)
+    res = {}
+    for lock in (None, 1e-11):
+        say("solve oscillator, lock_tol", lock)
+        plan = P.Plan(s.grid, s.box, 10, 4, "fp64")
+        plan.set_potential(s.V)
+        psi = plan.new_states(W.random_states(1, 10, s.grid))
+        r = P.solve(plan, psi, dt0=0.1, gamma=1e-10, lock_tol=lock)
+        say("  iters", r.iterations, "propagations", r.propagations, "max rel",
+            np.max(np.abs(r.eig[:10] - exact) / exact))
+        assert r.converged
+        assert np.max(np.abs(r.eig[:10] - exact) / exact) < 1e-10
+        assert plan.locked == 0
+        res[lock] = r
+    assert res[1e-11].propagations < res[None].propagations
+
+
 def test_batch_matches_individual_plans(P):
     """Uneven systems advanced as one batch equal separately planned systems bitwise
     (batched propagation launches over several systems, one graph per iteration)."""

@@ -229,6 +229,35 @@ def test_residual_e_zero_on_exact_eigenvectors():
     assert rh.max() < 1e-24
 
 
+@pytest.mark.parametrize("locked", [0, 2, 5])
+def test_locked_iteration_matches_dense_subspace(locked):
+    """Selective propagation (Section III): with the first ``locked`` states left
+    unpropagated, the iteration's Ritz pairs are those of H on
+    span{psi_0 .. psi_(locked-1), T psi_locked .. T psi_(m-1)}, built here from the
+    dense propagator matrix and a QR factorisation; R^E vanishes for the locked
+    states and equals the unlocked iteration's value for the others."""
+    grid, box = (8, 8, 8), (8.0, 8.0, 8.0)
+    V = toy8(grid, box)
+    m, K, dt = 5, 2, 0.3
+    Q0, _ = np.linalg.qr(W.random_states(21, m, grid).reshape(m, -1).T)
+    psi = Q0.T.reshape(m, *grid)
+    H = dense.hamiltonian_dense(V, grid, box)
+    M = dense.mpe_dense(V, grid, box, dt, K)
+    B = Q0.copy()
+    B[:, locked:] = M @ Q0[:, locked:]
+    Qb, _ = np.linalg.qr(B)
+    want = np.linalg.eigvalsh(Qb.T @ H @ Qb)
+    r = mpe.iterate(psi, V, dt, K, grid, box, locked=locked)
+    np.testing.assert_allclose(r.theta, want, rtol=1e-11, atol=1e-12)
+    # the output block spans the same subspace
+    P = r.psi.reshape(m, -1).T
+    assert np.abs(P @ (P.T @ Qb) - Qb).max() < 1e-10
+    full = mpe.iterate(psi, V, dt, K, grid, box)
+    assert np.abs(r.re[:locked]).max(initial=0.0) < 1e-14 and np.abs(r.re_perp[:locked]).max(initial=0.0) < 1e-14
+    np.testing.assert_allclose(r.re[locked:], full.re[locked:], rtol=1e-12, atol=1e-20)
+    np.testing.assert_allclose(r.re_perp[locked:], full.re_perp[locked:], rtol=1e-10, atol=1e-20)
+
+
 # ------------------------------------------------------------------ harmonic oscillator
 def test_separable_oscillator_levels():
     e = dense.separable_oscillator_levels(32, 16.0, 10)

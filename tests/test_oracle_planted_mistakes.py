@@ -58,6 +58,13 @@ def _mpe_wrong_substep(psi, V, dt, K, grid, box, hbar2_over_m=1.0):
     return acc
 
 
+_REAL_ITERATE = mpe.iterate
+
+
+def _iterate_lock_off_by_one(psi, V, dt, K, grid, box, hbar2_over_m=1.0, keep_phi=False, locked=0):
+    return _REAL_ITERATE(psi, V, dt, K, grid, box, hbar2_over_m, keep_phi, locked + 1 if locked else 0)
+
+
 CASES = [
     ("kinetic symbol without the 1/2", "kinetic_symbol", _ks_no_half,
      [(pins.test_h_apply_matches_dense, ((8, 8, 8), (8.0, 8.0, 8.0)))]),
@@ -69,6 +76,8 @@ CASES = [
      [(pins.test_t2_matches_dense, ((8, 8, 8), (8.0, 8.0, 8.0), 0.4))]),
     ("sub-step dt/k^2 in the expansion", "mpe_apply", _mpe_wrong_substep,
      [(pins.test_mpe_apply_matches_dense_expansion, (2,))]),
+    ("one state too many left unpropagated", "iterate", _iterate_lock_off_by_one,
+     [(pins.test_locked_iteration_matches_dense_subspace, (2,))]),
 ]
 
 
