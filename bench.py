@@ -148,6 +148,9 @@ def main():
     ap.add_argument("--solve", action="store_true",
                     help="also time a full solve to max R^H <= 1e-8 from a random start (float32 iterations, "
                          "float64 once float32 stalls)")
+    ap.add_argument("--lock", type=float, default=3.0, metavar="F",
+                    help="selective propagation in --solve: lock states below F*gamma in float32 and gamma/10 in "
+                         "float64 (0: propagate every state)")
     ap.add_argument("--workload", default="c60", choices=["c60", "batch"],
                     help="c60: the C60-like cage (default); batch: 64 uneven random molecules advanced "
                          "together (one graph replay per iteration), timed against separate plans")
@@ -263,9 +266,12 @@ def main():
         plan64 = P.Plan(s.grid, s.box, n_states, args.order, "fp64", n_guard=n_guard)
         plan64.set_potential(s.V)
         psi2 = plan.new_states(W.random_states(7, m, s.grid))
-        res = P.solve_ladder(plan, plan64, psi2, dt0=0.5, gamma=1e-8, n_check=n_states)
+        locks = (args.lock * 1e-8, 1e-9) if args.lock > 0 else (None, None)
+        res = P.solve_ladder(plan, plan64, psi2, dt0=0.5, gamma=1e-8, n_check=n_states, lock32=locks[0],
+                             lock64=locks[1])
         result["solve"] = {"seconds": round(res.seconds, 3), "iterations": res.iterations, "levels": res.levels,
-                           "converged": res.converged, "final_dt": res.dt, "start": "random", "stages": res.stages}
+                           "converged": res.converged, "final_dt": res.dt, "start": "random", "stages": res.stages,
+                           "state_propagations": res.propagations, "lock": args.lock}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(s, K, fsz)
     print(json.dumps(result))

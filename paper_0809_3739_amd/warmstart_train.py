@@ -169,12 +169,16 @@ def start_quality(plan: solver.Plan, psi: torch.Tensor) -> dict:
 
 
 def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, order: int = 12,
-                   gamma: float = 1e-8, variants=("learned_ladder", "random_ladder", "random_fp64"), log=print):
+                   gamma: float = 1e-8, variants=("learned_ladder_lock3", "random_ladder_lock3", "random_fp64_lock",
+                                                  "random_fp64"), log=print):
     """Iterations and seconds to max_{j<120} R^H_j < gamma from the learned and the random start.
 
     ``*_ladder``: float32 iterations until gamma or the float32 floor, then
     float64 (solver.solve_ladder); ``random_fp64``: float64 throughout.  The
-    random start is i.i.d. N(0, 1) from the geometry's seed.
+    random start is i.i.d. N(0, 1) from the geometry's seed.  A ``_lock<f>``
+    suffix adds selective propagation: states are locked once their R^H is
+    below ``f * gamma`` (f = 1 when omitted) in float32 and below ``gamma / 10``
+    in float64.
     """
     box = (BOX,) * 3
     p32 = solver.Plan((grid,) * 3, box, N_STATES, order, "fp32", n_guard=n_guard)
@@ -192,33 +196,38 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
         p64.set_potential(V)
         row = {"seed": int(s)}
         for var in variants:
+            base, _, lf = var.partition("_lock")
+            lock = "_lock" in var
+            lock32, lock64 = ((float(lf) if lf else 1.0) * gamma, 0.1 * gamma) if lock else (None, None)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            if var.startswith("learned"):
+            if base.startswith("learned"):
                 psi = learned_start(net, s, grid, n_guard)
             else:
                 psi = p32.new_states(W.random_states(s, m, (grid,) * 3))
-            if var.endswith("fp64"):
+            if base.endswith("fp64"):
                 psi = psi.to(torch.float64)
                 q = start_quality(p64, psi)
-                r = solver.solve(p64, psi, gamma=gamma, n_check=N_STATES, callback=progress)
+                r = solver.solve(p64, psi, gamma=gamma, n_check=N_STATES, callback=progress, lock_tol=lock64)
             else:
                 q = start_quality(p32, psi)
-                r = solver.solve_ladder(p32, p64, psi, gamma=gamma, n_check=N_STATES, callback=progress)
+                r = solver.solve_ladder(p32, p64, psi, gamma=gamma, n_check=N_STATES, callback=progress,
+                                        lock32=lock32, lock64=lock64)
             torch.cuda.synchronize()
             secs = time.perf_counter() - t0
             row[var] = {"start_max_rh": q["max_rh"], "first_iteration_max_rh": r.history[0]["rh"],
-                        "iterations": r.iterations, "seconds": round(secs, 3),
+                        "iterations": r.iterations, "propagations": r.propagations, "seconds": round(secs, 3),
                         "converged": bool(r.converged), "max_rh": float(np.max(r.rh[:N_STATES])),
                         "stages": r.stages, "eig": [float(e) for e in r.eig[:N_STATES]]}
             log(f"[eval] seed {s} {var}: start R^H {q['max_rh']:.3e}, after one iteration "
-                f"{r.history[0]['rh']:.3e} -> {r.iterations} it, {secs:.1f}s, "
+                f"{r.history[0]['rh']:.3e} -> {r.iterations} it ({r.propagations} state propagations), {secs:.1f}s, "
                 f"converged {r.converged}, stages {r.stages}")
             del psi
-        if "random_fp64" in row:
-            ref = np.array(row["random_fp64"]["eig"])
+        refv = "random_fp64" if "random_fp64" in row else ("random_fp64_lock" if "random_fp64_lock" in row else None)
+        if refv:
+            ref = np.array(row[refv]["eig"])
             for var in variants:
-                if var != "random_fp64":
+                if var != refv:
                     row[var]["max_rel_eig_diff_vs_fp64"] = float(np.max(np.abs(np.array(row[var]["eig"]) - ref)
                                                                         / np.abs(ref)))
         rows.append(row)
@@ -260,7 +269,7 @@ def main(argv=None):
     ap.add_argument("--eval-grid", type=int, default=128)
     ap.add_argument("--guards", type=int, default=5)
     ap.add_argument("--eval-gamma", type=float, default=1e-8)
-    ap.add_argument("--variants", default="learned_ladder,random_ladder,random_fp64")
+    ap.add_argument("--variants", default="learned_ladder_lock3,random_ladder_lock3,random_fp64_lock,random_fp64")
     a = ap.parse_args(argv)
 
     def log(msg):
