@@ -494,6 +494,16 @@ def test_solve_with_locking_oscillator(P):
     assert res[1e-11].propagations < res[None].propagations
 
 
+def test_order_study_runs(P):
+    """The order-comparison driver on a small case: every order converges to the same levels."""
+    from paper_0809_3739_amd import order_study
+    say("order study 16^3")
+    rows = order_study.run(grid=16, orders=(2, 6), n_states=6, n_guard=2, gamma=1e-7, log=lambda m: None)
+    assert all(r["converged"] for r in rows)
+    assert abs(rows[0]["eig0"] - rows[1]["eig0"]) < 1e-6
+    assert rows[1]["t2_per_state"] == rows[1]["state_propagations"] * 6 // 8
+
+
 def test_batch_matches_individual_plans(P):
     """Uneven systems advanced as one batch equal separately planned systems bitwise
     (batched propagation launches over several systems, one graph per iteration)."""
