@@ -500,7 +500,7 @@ def test_order_study_runs(P):
     say("order study 16^3")
     rows = order_study.run(grid=16, orders=(2, 6), n_states=6, n_guard=2, gamma=1e-7, log=lambda m: None)
     assert all(r["converged"] for r in rows)
-    assert abs(rows[0]["eig0"] - rows[1]["eig0"]) < 1e-6
+    assert abs(rows[0]["eig0"] - rows[1]["eig0"]) < 1e-5
     assert rows[1]["t2_per_state"] == rows[1]["state_propagations"] * 6 // 8
 
 
