@@ -176,6 +176,38 @@ def test_rayleigh_ritz_matches_oracle(P, prec, m, grid):
     assert np.allclose(rh[sep], rh_ref[sep], rtol=1e-6 if prec == "fp64" else 1e-2, atol=1e-20)
 
 
+@pytest.mark.parametrize("m", [1, 2, 3, 17, 63, 64, 65, 127, 128])
+def test_small_dense_edge_sizes(P, m):
+    """Block sizes at the edges of the small dense solver's layouts (one state, odd
+    counts padded for the Jacobi ordering, a partial last 16-tile, 64 and 128 rows
+    where the replay's second lane slot starts and ends): Cholesky orthonormalisation
+    and Rayleigh-Ritz against the oracle, float64."""
+    grid, box = (16, 16, 16), (10.0, 10.0, 10.0)
+    say("small dense edge size m", m)
+    V = toy_potential(grid, box)
+    phi = W.random_states(41, m, grid)
+    phi = oracle.t2(phi, V, 0.3, grid, box)
+    plan = P.Plan(grid, box, m, 2, "fp64", n_guard=0)
+    plan.set_potential(V)
+    psi = plan.new_states(phi)
+    plan.orthonormalize(psi)
+    ref, _, _ = oracle.cholesky_orthonormalize(phi)
+    got = psi.cpu().numpy()
+    say("  orthonormalise rel err", rel_err(got, ref))
+    assert rel_err(got, ref) < 1e-11
+    eig = plan.rayleigh_ritz(psi)
+    theta, Pr, _, _ = oracle.rayleigh_ritz(ref, oracle.h_apply(ref, V, grid, box))
+    e = np.max(np.abs(eig - theta)) / np.max(np.abs(theta))
+    G = psi.cpu().numpy().reshape(m, -1)
+    R = Pr.reshape(m, -1)
+    proj = np.abs(G.T @ (G @ R.T) - R.T).max()
+    HG = oracle.h_apply(G.reshape(m, *grid), V, grid, box).reshape(m, -1)
+    offd = np.abs(G @ HG.T - np.diag(eig)).max()
+    say(f"  eig rel {e:.2e} subspace {proj:.2e} H off-diagonal {offd:.2e} orth {np.abs(G @ G.T - np.eye(m)).max():.2e}")
+    assert e < 1e-11 and proj < 1e-9 and offd < 1e-9
+    assert np.abs(G @ G.T - np.eye(m)).max() < 1e-12
+
+
 @pytest.mark.parametrize("m,grid", [(20, (32, 32, 32)), (125, (16, 16, 16))])
 def test_float32_overlap_gemms(P, m, grid):
     """Float32 plans with the float32-MFMA overlap GEMMs: orthonormality and Ritz
