@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--dt", type=float, default=0.5)
     ap.add_argument("--states-per-launch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--gemm", default="fp64", choices=["fp64", "fp32"],
+    ap.add_argument("--gemm", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"],
                     help="overlap GEMMs on float64 MFMA (default) or float32 MFMA (float32 plans)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default plane-pass shapes instead of timing the candidates first")

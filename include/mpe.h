@@ -190,9 +190,15 @@ mpe_status mpe_set_plane_shape(mpe_plan p, int32_t kernel_class, int32_t mode, i
  * accumulation over slabs of 32 points and float64 sums across slabs and
  * chunks -- the float32 half of the precision split; overlaps then carry
  * ~1e-7 relative error, so the Cholesky pivot test becomes 1e-5 of the
- * diagonal.  The rotation of float32 plans always runs on float32 MFMA.
- * MPE_ERR_UNSUPPORTED for MPE_GEMM_FP32 on a float64 plan. */
-enum { MPE_GEMM_FP64 = 0, MPE_GEMM_FP32 = 1 };
+ * diagonal.  MPE_GEMM_BF16X3 / MPE_GEMM_BF16X6 (float32 plans only): every
+ * float32 value is split into 2 / 3 bfloat16 parts and the products of parts
+ * up to the matching order (3 / 6 products) run on bf16 MFMA with float32
+ * accumulation over 32-point slabs and float64 sums: ~1e-5 / ~1e-7 relative
+ * error, pivot tests 1e-3 / 1e-5 (two parts leave the variances R^E, which
+ * subtract overlaps near 1, as noise below ~1e-6).  The rotation of float32 plans always runs on
+ * float32 MFMA.  MPE_ERR_UNSUPPORTED for any mode but MPE_GEMM_FP64 on a
+ * float64 plan; MPE_ERR_INVALID_ARGUMENT for an unknown mode. */
+enum { MPE_GEMM_FP64 = 0, MPE_GEMM_FP32 = 1, MPE_GEMM_BF16X3 = 2, MPE_GEMM_BF16X6 = 3 };
 mpe_status mpe_set_gemm_precision(mpe_plan p, int32_t mode);
 
 /* Current shapes: shape[4] = {fwd mode, fwd blocks_per_cu, link mode, link blocks_per_cu}. */

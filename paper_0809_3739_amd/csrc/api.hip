@@ -492,6 +492,7 @@ mpe_status run_gram(mpe_plan p, const void* const* X, const void* const* Y, int 
   Timer t;
   tic(p, t, MPE_KC_GRAM);
   if (!p->dbl && p->gemm == 1) HIPCHK(p, launch_gram32(g, nprod, nch, p->st));
+  else if (!p->dbl && p->gemm >= 2) HIPCHK(p, launch_gramb(g, nprod, nch, p->gemm == 2 ? 2 : 3, p->st));
   else HIPCHK(p, launch_gram(p->dbl, g, nprod, nch, p->st));
   HIPCHK(p, launch_reduce(p->partials, nch, (long)p->mp * p->mp, nprod, out0, p->st));
   toc(p, t);
@@ -1042,14 +1043,14 @@ mpe_status mpe_set_plane_shape(mpe_plan p, int32_t kernel_class, int32_t mode, i
 
 mpe_status mpe_set_gemm_precision(mpe_plan p, int32_t mode) {
   if (!p) return MPE_ERR_INVALID_ARGUMENT;
-  if (mode != MPE_GEMM_FP64 && mode != MPE_GEMM_FP32)
-    return fail(p, MPE_ERR_INVALID_ARGUMENT, "mode must be MPE_GEMM_FP64 or MPE_GEMM_FP32");
-  if (mode == MPE_GEMM_FP32 && p->dbl)
-    return fail(p, MPE_ERR_UNSUPPORTED, "float32 overlap GEMMs are for float32 plans");
-  p->gemm = mode == MPE_GEMM_FP32 ? 1 : 0;
-  // overlaps now carry ~1e-7 relative error: a pivot below 1e-5 of its diagonal
-  // marks linearly dependent states
-  p->pivot_tol = p->gemm ? 1e-5 : 1e-13;
+  if (mode < MPE_GEMM_FP64 || mode > MPE_GEMM_BF16X6)
+    return fail(p, MPE_ERR_INVALID_ARGUMENT, "mode must be one of MPE_GEMM_FP64, FP32, BF16X3, BF16X6");
+  if (mode != MPE_GEMM_FP64 && p->dbl)
+    return fail(p, MPE_ERR_UNSUPPORTED, "float32 and BF16-split overlap GEMMs are for float32 plans");
+  p->gemm = mode;
+  // overlaps now carry ~1e-7 (float32, BF16x6) or ~1e-5 (BF16x3) relative error: a
+  // pivot below 1e-5 (1e-3) of its diagonal marks linearly dependent states
+  p->pivot_tol = p->gemm == MPE_GEMM_FP64 ? 1e-13 : (p->gemm == MPE_GEMM_BF16X3 ? 1e-3 : 1e-5);
   p->shape_ver++;   // re-capture the iteration graph
   return MPE_OK;
 }

@@ -249,6 +249,137 @@ __global__ __launch_bounds__(512) void gram32_partial_kernel(GramArgs g) {
   }
 }
 
+// BF16-split variant for float32 states: every staged value x is split into
+// SPLIT bfloat16 parts (x = h + m + l up to the last bits: h = bf16(x), then the
+// exact float32 remainder is split again), and X Y^T is formed from the
+// products of parts whose orders add up to at most SPLIT - 1 (SPLIT = 2: hh,
+// hl, lh, ~16 significant bits; SPLIT = 3: hh, hm, mh, hl, mm, lh, ~24 bits)
+// on v_mfma_f32_16x16x32_bf16, smallest terms first, float32 accumulation over
+// the 32-point slab and float64 sums across slabs.  Parts are staged in LDS as
+// [part][state][point] (rows padded to 40 bf16), so the 8 consecutive points a
+// lane feeds to one MFMA are one 16-byte read.
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);   // inf / nan kept
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int NT, int MODE, int SPLIT>
+__global__ __launch_bounds__(512) void gramb_partial_kernel(GramArgs g) {
+  constexpr bool ONE = MODE == GRAM_SELF, TRI = MODE != GRAM_FULL;
+  constexpr int W = 8;
+  constexpr int mp = NT * 16;
+  constexpr int NTILE = GramTiles<NT, TRI>::count;
+  constexpr int TPW = (NTILE + W - 1) / W;
+  constexpr int PER = (mp * GSLAB + 511) / 512;
+  constexpr int RS = GSLAB + 8;   // bf16 per staged row (80 bytes)
+  static_assert(GSLAB == 32, "one 16x16x32 MFMA per slab and part pair");
+  __shared__ __align__(16) unsigned short xs[SPLIT][mp][RS];
+  __shared__ __align__(16) unsigned short ys[ONE ? 1 : SPLIT][ONE ? 1 : mp][ONE ? 8 : RS];
+  const int prod = blockIdx.y;
+  const float* __restrict__ X = reinterpret_cast<const float*>(g.X[prod]);
+  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y[prod]);
+  const int m = g.m;
+  const long N = g.N;
+  const long p_begin = (long)blockIdx.x * g.chunk;
+  const long p_end = min(N, p_begin + g.chunk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int tiv[TPW], tjv[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int u = wave + W * t;
+    tile_coords(u < NTILE ? u : 0, NT, TRI, tiv[t], tjv[t]);
+  }
+  d4 sum[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) sum[t] = d4{0.0, 0.0, 0.0, 0.0};
+  float px[PER], py[PER];
+  auto load = [&](long p0) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 512 * r;
+      const int st = e / GSLAB, q = e - st * GSLAB;
+      const long p = p0 + q;
+      const bool ok = e < mp * GSLAB && st < m && p < p_end;
+      const long idx = ok ? (long)st * N + p : 0;   // unconditional loads, no exec-mask branches
+      const float vx = X[idx];
+      px[r] = ok ? vx : 0.f;
+      if (!ONE) {
+        const float vy = Y[idx];
+        py[r] = ok ? vy : 0.f;
+      }
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 512 * r;
+      if (e < mp * GSLAB) {
+        const int st = e / GSLAB, q = e - st * GSLAB;
+        float x = px[r];
+#pragma unroll
+        for (int s = 0; s < SPLIT; ++s) {
+          const unsigned short h = bf16_rne(x);
+          xs[s][st][q] = h;
+          x -= bf16_f(h);
+        }
+        if (!ONE) {
+          float y = py[r];
+#pragma unroll
+          for (int s = 0; s < SPLIT; ++s) {
+            const unsigned short h = bf16_rne(y);
+            ys[s][st][q] = h;
+            y -= bf16_f(h);
+          }
+        }
+      }
+    }
+  };
+  auto part = [&](int s, int state, bool from_y) -> bf16x8 {
+    const unsigned short* row = (ONE || !from_y) ? &xs[s][state][0] : &ys[s][state][0];
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(row + 8 * (lane >> 4)));
+  };
+  load(p_begin);
+  for (long p0 = p_begin; p0 < p_end; p0 += GSLAB) {
+    stage();
+    __syncthreads();
+    if (p0 + GSLAB < p_end) load(p0 + GSLAB);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      if (TPW * W == NTILE || wave + W * t < NTILE) {
+        const int si = tiv[t] * 16 + (lane & 15), sj = tjv[t] * 16 + (lane & 15);
+        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+        // part pairs by decreasing order sum (smallest products first)
+#pragma unroll
+        for (int o = SPLIT - 1; o >= 0; --o)
+#pragma unroll
+          for (int a = o; a >= 0; --a)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(part(a, si, false), part(o - a, sj, true), acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sum[t][r] += (double)acc[r];
+      }
+    }
+    __syncthreads();
+  }
+  double* out = g.partials + ((long)prod * gridDim.x + blockIdx.x) * (long)mp * mp;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    if (wave + W * t < NTILE) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = tiv[t] * 16 + 4 * (lane >> 4) + r, j = tjv[t] * 16 + (lane & 15);   // f32 D layout
+        out[(long)i * mp + j] = sum[t][r];
+        if (TRI && tiv[t] != tjv[t]) out[(long)j * mp + i] = sum[t][r];
+      }
+    }
+  }
+}
+
 // out[c][e] = sum_{q < nparts} in[c][q][e], e < count, fixed order.
 __global__ void reduce_kernel(const double* __restrict__ in, int nparts, long count, double* __restrict__ out) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -861,6 +992,45 @@ static hipError_t launch_gram32_t(const GramArgs& g, int nchunks, hipStream_t st
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int MODE, int SPLIT>
+static hipError_t launch_gramb_t(const GramArgs& g, int nchunks, hipStream_t st) {
+  dim3 grid(nchunks, 1), block(512);
+  switch (g.mp / 16) {
+    case 1: hipLaunchKernelGGL((gramb_partial_kernel<1, MODE, SPLIT>), grid, block, 0, st, g); break;
+    case 2: hipLaunchKernelGGL((gramb_partial_kernel<2, MODE, SPLIT>), grid, block, 0, st, g); break;
+    case 3: hipLaunchKernelGGL((gramb_partial_kernel<3, MODE, SPLIT>), grid, block, 0, st, g); break;
+    case 4: hipLaunchKernelGGL((gramb_partial_kernel<4, MODE, SPLIT>), grid, block, 0, st, g); break;
+    case 5: hipLaunchKernelGGL((gramb_partial_kernel<5, MODE, SPLIT>), grid, block, 0, st, g); break;
+    case 6: hipLaunchKernelGGL((gramb_partial_kernel<6, MODE, SPLIT>), grid, block, 0, st, g); break;
+    case 7: hipLaunchKernelGGL((gramb_partial_kernel<7, MODE, SPLIT>), grid, block, 0, st, g); break;
+    case 8: hipLaunchKernelGGL((gramb_partial_kernel<8, MODE, SPLIT>), grid, block, 0, st, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int SPLIT>
+static hipError_t launch_gramb_split(const GramArgs& g, int nprod, int nchunks, hipStream_t st) {
+  for (int i = 0; i < nprod; ++i) {
+    GramArgs one = g;
+    one.X[0] = g.X[i];
+    one.Y[0] = g.Y[i];
+    one.partials = g.partials + (long)i * nchunks * g.mp * g.mp;
+    const int mode = gram_mode(g, i);
+    const hipError_t e = mode == GRAM_SELF    ? launch_gramb_t<GRAM_SELF, SPLIT>(one, nchunks, st)
+                         : mode == GRAM_UPPER ? launch_gramb_t<GRAM_UPPER, SPLIT>(one, nchunks, st)
+                                              : launch_gramb_t<GRAM_FULL, SPLIT>(one, nchunks, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_gramb(const GramArgs& g, int nprod, int nchunks, int split, hipStream_t st) {
+  if (split == 2) return launch_gramb_split<2>(g, nprod, nchunks, st);
+  if (split == 3) return launch_gramb_split<3>(g, nprod, nchunks, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_gram32(const GramArgs& g, int nprod, int nchunks, hipStream_t st) {

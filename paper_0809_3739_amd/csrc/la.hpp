@@ -60,6 +60,8 @@ struct RotateArgs {
 hipError_t launch_gram(int is_double, const GramArgs& g, int nprod, int nchunks, hipStream_t st);
 // float32 states only: float32 MFMA, float64 slab sums and partials
 hipError_t launch_gram32(const GramArgs& g, int nprod, int nchunks, hipStream_t st);
+// float32 states only: BF16-split products (split = 2 or 3 parts) on bf16 MFMA
+hipError_t launch_gramb(const GramArgs& g, int nprod, int nchunks, int split, hipStream_t st);
 hipError_t launch_reduce(const double* in, int nparts, long count, int ncomp, double* out, hipStream_t st);
 hipError_t prepare_small_dense();
 hipError_t launch_small_dense(const SmallDenseArgs& d, hipStream_t st);

@@ -153,8 +153,9 @@ class Plan:
         self._check(self.lib.mpe_set_plane_shape(self.h, kc, int(mode), int(blocks_per_cu)))
 
     def set_gemm_precision(self, mode: str):
-        """Overlap GEMMs in "fp64" (default) or "fp32" MFMA (float32 plans)."""
-        self._check(self.lib.mpe_set_gemm_precision(self.h, {"fp64": 0, "fp32": 1}[mode]))
+        """Overlap GEMMs in "fp64" (default), "fp32", "bf16x3" or "bf16x6" MFMA
+        (the last three for float32 plans; see mpe_set_gemm_precision)."""
+        self._check(self.lib.mpe_set_gemm_precision(self.h, {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}[mode]))
 
     def plane_shape(self) -> dict:
         buf = (C.c_int32 * 4)()

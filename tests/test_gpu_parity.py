@@ -249,6 +249,66 @@ def test_float32_overlap_gemms(P, m, grid):
         p64.set_gemm_precision("fp32")
 
 
+@pytest.mark.parametrize("mode,bar", [("bf16x6", 2e-6), ("bf16x3", 1e-4)])
+@pytest.mark.parametrize("m,grid", [(20, (32, 32, 32)), (125, (16, 16, 16))])
+def test_bf16_split_overlap_gemms(P, mode, bar, m, grid):
+    """BF16-split overlap GEMMs (3 or 6 bf16 MFMA products per float32 product):
+    Ritz values of an oracle-orthonormalised block and the orthonormality after
+    two Cholesky passes against the oracle, at bars set by the split's precision
+    (~2^-16 for two parts, ~2^-24 for three); float64 plans refuse the mode."""
+    say("bf16-split overlap gemms", mode, m, grid)
+    box = (10.0, 10.0, 10.0)
+    V = toy_potential(grid, box)
+    phi = W.random_states(31, m, grid)
+    for _ in range(3):
+        phi = oracle.t2(phi, V, 0.3, grid, box)
+    plan = P.Plan(grid, box, m, 2, "fp32")
+    plan.set_potential(V)
+    plan.set_gemm_precision(mode)
+    Psi0, _, _ = oracle.cholesky_orthonormalize(phi)
+    Psi0 = rounded(Psi0, "fp32")
+    psi = plan.new_states(Psi0)
+    eig = plan.rayleigh_ritz(psi)
+    theta, _, _, _ = oracle.rayleigh_ritz(Psi0, oracle.h_apply(Psi0, V, grid, box))
+    err = np.max(np.abs(eig - theta)) / np.max(np.abs(theta))
+    # Cholesky QR loses cond(Phi)^2 times the overlap error: the smoothed block (cond^2 ~ 1e5
+    # for 125 states on 16^3 points) is within reach of three parts, two parts get a
+    # well-conditioned block (an orthonormal one plus a 10 % perturbation)
+    x = phi if mode == "bf16x6" else Psi0 + 0.1 * W.random_states(37, m, grid) / math.sqrt(np.prod(grid))
+    psi = plan.new_states(x)
+    plan.orthonormalize(psi)
+    plan.orthonormalize(psi)
+    g = psi.cpu().numpy().astype(np.float64).reshape(m, -1)
+    ortho = np.max(np.abs(g @ g.T - np.eye(m)))
+    say(f"  eig err {err:.2e} orthonormality after two passes {ortho:.2e}")
+    assert err < 10 * bar
+    assert ortho < max(10 * bar, 1e-5)
+    p64 = P.Plan(grid, box, m, 2, "fp64")
+    from paper_0809_3739_amd import MpeError
+    with pytest.raises(MpeError):
+        p64.set_gemm_precision(mode)
+
+
+@pytest.mark.parametrize("mode,tol", [("bf16x6", 1e-6)])
+def test_bf16_split_gemms_solve_oscillator(P, mode, tol):
+    """The oscillator levels with BF16-split overlap GEMMs.  Three parts only: the
+    driver's per-step variance test (R^E_perp = S_jj - sum_i M_ij^2, a difference
+    of numbers near 1 that must resolve ~1e-11) needs overlaps to ~24 bits; with
+    two parts (~1e-6 relative) it reads noise and the step-size protocol stops
+    early, so that mode serves single Rayleigh-Ritz and orthonormalisation calls."""
+    s = W.harmonic_system(32, 16.0, 10)
+    say("solve oscillator", mode, "gemms")
+    plan = P.Plan(s.grid, s.box, 10, 4, "fp32")
+    plan.set_potential(s.V)
+    plan.set_gemm_precision(mode)
+    psi = plan.new_states(W.random_states(1, 10, s.grid))
+    res = P.solve(plan, psi, dt0=0.1, gamma=1e-9, max_levels=4)
+    exact = dense.separable_oscillator_levels(32, 16.0, 10)
+    err = np.max(np.abs(res.eig[:10] - exact) / np.abs(exact))
+    say("  eig rel err", err, "iterations", res.iterations, "max R^H", float(np.max(res.rh)))
+    assert err < tol
+
+
 def test_float32_gemms_solve_oscillator(P):
     """The oscillator levels with float32 overlap GEMMs (float32 bar)."""
     s = W.harmonic_system(32, 16.0, 10)
