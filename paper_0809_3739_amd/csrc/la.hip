@@ -460,9 +460,24 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   if (tid == 0) flag = -1;
   stamp(d, 0);
   __syncthreads();
-  // ---- Cholesky of S in LDS (right-looking)
+  // ---- Cholesky of S in LDS (right-looking, one barrier per pivot): step k
+  // updates the trailing lower triangle with column k unscaled,
+  // a_ij -= a_ik a_jk / p_k, and every column is scaled by 1/sqrt(p_k) once at
+  // the end.  Each thread owns fixed elements of the lower triangle.
   for (int e = tid; e < m * m; e += SD_THREADS) A(e / m, e % m) = d.S[(e / m) * (long)d.mp + e % m];
   for (int i = tid; i < m; i += SD_THREADS) dg[i] = d.S[i * (long)d.mp + i];
+  constexpr int CH_EL = (MAXM * (MAXM + 1) / 2 + SD_THREADS - 1) / SD_THREADS;
+  int el_i[CH_EL], el_j[CH_EL];
+#pragma unroll
+  for (int r = 0; r < CH_EL; ++r) {
+    const int t = tid + r * SD_THREADS;   // row-major index into the lower triangle
+    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > t) --i;
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    const bool ok = t < m * (m + 1) / 2;
+    el_i[r] = ok ? i : 0;
+    el_j[r] = ok ? t - i * (i + 1) / 2 : m;   // j = m: never updated
+  }
   __syncthreads();
   // A pivot that has lost all but ~13 digits of its original diagonal means the
   // states are linearly dependent to working precision: reported, not factored.
@@ -473,17 +488,27 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
       if (tid == 0 && flag < 0) flag = isfinite(piv) ? k : -2 - k;
       break;  // uniform: every thread sees the same pivot
     }
-    const double lkk = sqrt(piv);
-    __syncthreads();
-    for (int i = k + tid; i < m; i += SD_THREADS) A(i, k) = (i == k) ? lkk : A(i, k) / lkk;
-    __syncthreads();
-    const int rem = m - k - 1;
-    for (int e = tid; e < rem * rem; e += SD_THREADS) {
-      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-      if (j <= i) A(i, j) -= A(i, k) * A(j, k);
+    const double inv = 1.0 / piv;
+#pragma unroll
+    for (int r = 0; r < CH_EL; ++r) {
+      const int i = el_i[r], j = el_j[r];
+      if (j > k && j < m) A(i, j) -= A(i, k) * A(j, k) * inv;
     }
     __syncthreads();
   }
+  if (flag == -1) {   // scale the columns: L_ij = a_ij / sqrt(p_j), L_jj = sqrt(p_j)
+#pragma unroll
+    for (int r = 0; r < CH_EL; ++r) {
+      const int i = el_i[r], j = el_j[r];
+      if (j < m) {
+        const double pj = A(j, j);   // diagonal entries are only rewritten below, after the barrier
+        if (i != j) A(i, j) /= sqrt(pj);
+      }
+    }
+  }
+  __syncthreads();
+  if (flag == -1)
+    for (int i = tid; i < m; i += SD_THREADS) A(i, i) = sqrt(A(i, i));
   __syncthreads();
   if (flag != -1) {
     if (tid == 0) {
