@@ -381,14 +381,30 @@ __global__ __launch_bounds__(512) void gramb_partial_kernel(GramArgs g) {
 }
 
 // out[c][e] = sum_{q < nparts} in[c][q][e], e < count, fixed order.
-__global__ void reduce_kernel(const double* __restrict__ in, int nparts, long count, double* __restrict__ out) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+// Work-group: 64 elements x RD_SLICES wavefronts; wavefront w sums the parts
+// q = w, w + RD_SLICES, ... of its lane's element, then the slices are added
+// in slice order (a fixed order for every call).
+constexpr int RD_SLICES = 8;
+__global__ __launch_bounds__(64 * RD_SLICES) void reduce_kernel(const double* __restrict__ in, int nparts, long count,
+                                                                double* __restrict__ out) {
+  __shared__ double part[RD_SLICES][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long e = (long)blockIdx.x * 64 + lane;
   const int c = blockIdx.y;
-  if (e >= count) return;
-  const double* src = in + (long)c * nparts * count + e;
   double s = 0.0;
-  for (int q = 0; q < nparts; ++q) s += src[(long)q * count];
-  out[(long)c * count + e] = s;
+  if (e < count) {
+    const double* src = in + (long)c * nparts * count + e;
+#pragma unroll 8
+    for (int q = w; q < nparts; q += RD_SLICES) s += src[(long)q * count];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && e < count) {
+    double t = part[0][lane];
+#pragma unroll
+    for (int k = 1; k < RD_SLICES; ++k) t += part[k][lane];
+    out[(long)c * count + e] = t;
+  }
 }
 
 // ------------------------------------------------------------------ small dense problem
@@ -1095,8 +1111,8 @@ hipError_t launch_gram(int is_double, const GramArgs& g, int nprod, int nchunks,
 }
 
 hipError_t launch_reduce(const double* in, int nparts, long count, int ncomp, double* out, hipStream_t st) {
-  dim3 grid((unsigned)((count + 255) / 256), ncomp);
-  hipLaunchKernelGGL(reduce_kernel, grid, dim3(256), 0, st, in, nparts, count, out);
+  dim3 grid((unsigned)((count + 63) / 64), ncomp);
+  hipLaunchKernelGGL(reduce_kernel, grid, dim3(64 * RD_SLICES), 0, st, in, nparts, count, out);
   return hipGetLastError();
 }
 
