@@ -817,8 +817,8 @@ __global__ __launch_bounds__(64 * RP_ROWS) void sd_replay_kernel(SmallDenseArgs 
 // MT is the MFMA operand type: double (v_mfma_f64_16x16x4f64, float64 plans)
 // or float (v_mfma_f32_16x16x4f32, float32 plans: C rounded to float32, the
 // rotation of float32 states then loses nothing beyond float32 storage).
-// A strip's B operands are loaded in one go before its MFMA chain.
-
+// A strip's B operands are loaded in groups of KG k-steps, each group issued
+// before the MFMAs of the previous one.
 
 template <typename MT>
 struct Mfma;
