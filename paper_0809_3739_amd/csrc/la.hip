@@ -5,6 +5,8 @@
 // States are rows of an [m][N] array (m = states incl. guards, N grid points).
 //  * gram_partial_kernel : X Y^T over a chunk of points on float64 MFMA
 //    (v_mfma_f64_16x16x4f64); inputs of either precision are widened exactly.
+//  * gram32_partial_kernel / gramb_partial_kernel : the same for float32 states
+//    on float32 MFMA, or on bf16 MFMA with the values split into bf16 parts.
 //  * reduce_kernel       : fixed-order float64 sum of chunk partials.
 //  * small_dense_kernel  : one work-group; S = L L^T, A = L^-1 Hs L^-T,
 //    cyclic parallel Jacobi on A (rotations logged), eigenvalues sorted, L^-T.
