@@ -169,8 +169,8 @@ def start_quality(plan: solver.Plan, psi: torch.Tensor) -> dict:
 
 
 def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, order: int = 12,
-                   gamma: float = 1e-8, variants=("learned_ladder_lock3", "random_ladder_lock3", "random_fp64_lock",
-                                                  "random_fp64"), log=print):
+                   gamma: float = 1e-8, variants=("learned_ladder_lock3_g32", "random_ladder_lock3_g32",
+                                                  "random_fp64_lock", "random_fp64"), log=print):
     """Iterations and seconds to max_{j<120} R^H_j < gamma from the learned and the random start.
 
     ``*_ladder``: float32 iterations until gamma or the float32 floor, then
@@ -178,7 +178,8 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
     random start is i.i.d. N(0, 1) from the geometry's seed.  A ``_lock<f>``
     suffix adds selective propagation: states are locked once their R^H is
     below ``f * gamma`` (f = 1 when omitted) in float32 and below ``gamma / 10``
-    in float64.
+    in float64.  A final ``_g32`` runs the float32 stage's overlaps on float32
+    MFMA.
     """
     box = (BOX,) * 3
     p32 = solver.Plan((grid,) * 3, box, N_STATES, order, "fp32", n_guard=n_guard)
@@ -196,8 +197,11 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
         p64.set_potential(V)
         row = {"seed": int(s)}
         for var in variants:
-            base, _, lf = var.partition("_lock")
-            lock = "_lock" in var
+            g32 = var.endswith("_g32")
+            name = var[:-4] if g32 else var
+            base, _, lf = name.partition("_lock")
+            lock = "_lock" in name
+            p32.set_gemm_precision("fp32" if g32 else "fp64")
             lock32, lock64 = ((float(lf) if lf else 1.0) * gamma, 0.1 * gamma) if lock else (None, None)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -269,7 +273,7 @@ def main(argv=None):
     ap.add_argument("--eval-grid", type=int, default=128)
     ap.add_argument("--guards", type=int, default=5)
     ap.add_argument("--eval-gamma", type=float, default=1e-8)
-    ap.add_argument("--variants", default="learned_ladder_lock3,random_ladder_lock3,random_fp64_lock,random_fp64")
+    ap.add_argument("--variants", default="learned_ladder_lock3_g32,random_ladder_lock3_g32,random_fp64_lock,random_fp64")
     a = ap.parse_args(argv)
 
     def log(msg):
