@@ -161,7 +161,11 @@ mpe_status mpe_small_dense_phases(mpe_plan p, double* us);
  * the overlaps, the Rayleigh-Ritz rotation and the variances as Phi_j = Psi_j
  * (so their R^E and R^E_perp come out as 0), while states locked..m-1 are
  * propagated as usual and the whole block is orthonormalised and rotated.
- * R^H is evaluated for every state.  0 <= locked <= m, else
+ * R^H is evaluated for every state.  When the previous call on this plan was
+ * mpe_iterate or mpe_rayleigh_ritz on the same block (nothing has touched it
+ * since), H Psi_j of the locked states is taken from that call's rotation
+ * instead of applying H again; the caller must not modify the block between
+ * such calls.  0 <= locked <= m, else
  * MPE_ERR_INVALID_ARGUMENT; 0 (the default) propagates every state.  Applies
  * to mpe_iterate only (mpe_step always propagates the whole block). */
 mpe_status mpe_set_locked(mpe_plan p, int32_t locked);

@@ -160,6 +160,7 @@ struct mpe_plan_s {
   double last_dt = -1.0;
   int states_per_launch = 0;
   int locked = 0;                    // leading states mpe_iterate leaves unpropagated
+  int hfirst = 0;                    // first state whose H phi the next iteration computes
   // launch shapes of the forward [0] and link [1] plane passes (PlaneArgs::persist_mode,
   // work-groups per CU); shape_ver counts changes so a captured graph can notice them
   int pmode[2] = {0, 0};
@@ -180,6 +181,7 @@ struct mpe_plan_s {
   const void* g_psi = nullptr;       // the graph bakes in this state block ...
   int g_spl = -1;                    // ... and this launch grouping
   int g_locked = -1;                 // ... and this number of locked states
+  int g_hfirst = -1;                 // ... and this first H state
   int g_shape = -1;                  // ... and these plane-pass shapes
   hipEvent_t ev_in = nullptr;
   int64_t graph_launches = 0;
@@ -419,8 +421,8 @@ mpe_status run_step(mpe_plan p, const void* src, void* dst, double dt) {
   return s;
 }
 
-// hdst <- H src (src != hdst); uses chain 0's spectrum buffer as scratch.
-mpe_status run_h(mpe_plan p, const void* src, void* hdst) {
+// hdst <- H src for states [first, m) (src != hdst); uses chain 0's spectrum buffer as scratch.
+mpe_status run_h(mpe_plan p, const void* src, void* hdst, int first = 0) {
   if (!p->have_v) return fail(p, MPE_ERR_STATE, "no potential set (mpe_set_potential)");
   if (p->tab_dt < 0) {
     mpe_status s = ensure_tables(p, 1.0);  // builds the additive table (independent of dt)
@@ -449,7 +451,7 @@ mpe_status run_h(mpe_plan p, const void* src, void* hdst) {
            c.real_out = hdst;
            c.state0 = s0;
            return launch_plane(p->dbl, PM_HTAIL, p->nx, c, p->nz, cnt, p->st);
-         }));
+         }, first));
   toc(p, t);
   return MPE_OK;
 }
@@ -606,7 +608,9 @@ mpe_status enqueue_iterate(mpe_plan p, void* psi) {
   // enter the overlaps and the rotation unpropagated: Phi_j = Psi_j
   if (p->locked > 0) HIPCHK(p, launch_copy16(p->phi, psi, (size_t)p->locked * p->N * p->fsz, p->st));
   mpe_status s = enqueue_step(p, psi, p->phi, p->locked);
-  if (s == MPE_OK) s = run_h(p, p->phi, p->hphi);
+  // H Phi_j = H Psi_j of the locked states is still in hphi from the previous
+  // rotation when nothing touched psi since (p->hfirst > 0 only then)
+  if (s == MPE_OK) s = run_h(p, p->phi, p->hphi, p->hfirst);
   const void* X[3] = {p->phi, p->phi, psi};
   const void* Y[3] = {p->phi, p->hphi, p->phi};
   if (s == MPE_OK) s = run_gram(p, X, Y, 3, p->S(), 2);   // S, Hs (upper tiles), M contiguous
@@ -629,6 +633,7 @@ void drop_graph(mpe_plan p) {
   p->g_psi = nullptr;
   p->g_spl = -1;
   p->g_locked = -1;
+  p->g_hfirst = -1;
   p->g_shape = -1;
 }
 
@@ -654,6 +659,7 @@ mpe_status capture_iterate(mpe_plan p, void* psi) {
   p->g_psi = psi;
   p->g_spl = p->states_per_launch;
   p->g_locked = p->locked;
+  p->g_hfirst = p->hfirst;
   p->g_shape = p->shape_ver;
   return MPE_OK;
 }
@@ -967,13 +973,16 @@ mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh
   if (!p) return MPE_ERR_INVALID_ARGUMENT;
   if (!psi) return fail(p, MPE_ERR_INVALID_ARGUMENT, "psi is null");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, MPE_ERR_INVALID_ARGUMENT, "dt must be positive");
+  // hphi holds H psi (the previous iteration's or Rayleigh-Ritz rotation) only
+  // when no call has touched psi since: then locked states reuse it
+  p->hfirst = (p->locked > 0 && p->rr_cache_psi == psi) ? p->locked : 0;
   p->rr_cache_psi = nullptr;
   mpe_status s = ensure_tables(p, dt);
   if (s != MPE_OK) return s;
   p->last_dt = dt;
   if (p->use_graph && !p->prof) {
     if (!p->gexec || p->g_psi != psi || p->g_spl != p->states_per_launch || p->g_shape != p->shape_ver ||
-        p->g_locked != p->locked) {
+        p->g_locked != p->locked || p->g_hfirst != p->hfirst) {
       s = capture_iterate(p, psi);
       if (s != MPE_OK) return s;
     }

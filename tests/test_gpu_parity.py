@@ -554,6 +554,36 @@ def test_locked_graph_replay_matches_eager(P):
             assert np.array_equal(x, y)
 
 
+def test_locked_states_reuse_h_from_the_rotation(P):
+    """Consecutive locked iterations take H Psi of the locked states from the previous
+    rotation instead of applying H again; the results match iterations that recompute
+    it (a call in between drops the cached H Psi) to float64 rounding."""
+    grid, box = (32, 32, 32), (12.0, 12.0, 12.0)
+    say("locked states reuse H from the rotation")
+    V = toy_potential(grid, box)
+    psi0 = W.random_states(6, 8, grid)
+    runs = []
+    for fresh_h in (False, True):
+        plan = P.Plan(grid, box, 8, 6, "fp64")
+        plan.set_potential(V)
+        psi = plan.new_states(psi0)
+        plan.orthonormalize(psi)
+        outs = []
+        for locked in (0, 3, 3, 5, 2):
+            plan.set_locked(locked)
+            if fresh_h:
+                h = plan.apply_h(psi)   # leaves psi alone, drops the cached H psi
+                del h
+            r = plan.iterate(psi, 0.3)
+            outs.append((psi.cpu().numpy().copy(), r["eig"].copy(), r["rh"].copy()))
+        runs.append(outs)
+    for (pa, ea, ra), (pb, eb, rb) in zip(*runs):
+        assert rel_err(ea, eb) < 1e-12
+        assert np.max(np.abs(ra - rb)) < 1e-12 * max(np.max(rb), 1e-30) + 1e-24
+        Pa, Pb = pa.reshape(8, -1), pb.reshape(8, -1)
+        assert np.abs(Pa.T @ (Pa @ Pb.T) - Pb.T).max() < 1e-10
+
+
 def test_locked_bounds(P):
     grid, box = (16, 16, 16), (8.0, 8.0, 8.0)
     say("locked bounds")
