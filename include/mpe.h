@@ -169,6 +169,13 @@ mpe_status mpe_small_dense_phases(mpe_plan p, double* us);
  * MPE_ERR_INVALID_ARGUMENT; 0 (the default) propagates every state.  Applies
  * to mpe_iterate only (mpe_step always propagates the whole block). */
 mpe_status mpe_set_locked(mpe_plan p, int32_t locked);
+/* Whether the following mpe_iterate calls form the overlap M = Psi^T Phi and
+ * the variances R^E, R^E_perp (on != 0, the default) or skip them (their
+ * outputs are then NaN; eigenvalues and R^H are unaffected).  A driver that
+ * needs the variances only now and then saves one of the three overlap
+ * products in the other iterations. */
+mpe_status mpe_set_variances(mpe_plan p, int32_t on);
+
 /* Current number of locked states (-1 for a null plan). */
 int32_t mpe_get_locked(mpe_plan p);
 

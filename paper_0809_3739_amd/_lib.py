@@ -50,6 +50,7 @@ SIGNATURES = {
     "mpe_iterate": (C.c_int, [_vp, _vp, C.c_double, _dp, _dp, _dp, _dp]),
     "mpe_set_states_per_launch": (C.c_int, [_vp, _i32]),
     "mpe_set_locked": (C.c_int, [_vp, _i32]),
+    "mpe_set_variances": (C.c_int, [_vp, _i32]),
     "mpe_get_locked": (_i32, [_vp]),
     "mpe_set_plane_shape": (C.c_int, [_vp, _i32, _i32, _i32]),
     "mpe_get_plane_shape": (C.c_int, [_vp, C.POINTER(_i32)]),

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -176,13 +177,17 @@ struct mpe_plan_s {
   // graph replay of the fused iteration
   bool use_graph = true;
   hipStream_t gst = nullptr;         // private stream for capture and replay
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  const void* g_psi = nullptr;       // the graph bakes in this state block ...
-  int g_spl = -1;                    // ... and this launch grouping
-  int g_locked = -1;                 // ... and this number of locked states
-  int g_hfirst = -1;                 // ... and this first H state
-  int g_shape = -1;                  // ... and these plane-pass shapes
+  // one captured iteration per variance setting (slot = variances on)
+  struct IterGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* psi = nullptr;       // the graph bakes in this state block ...
+    int spl = -1;                    // ... and this launch grouping
+    int locked = -1;                 // ... and this number of locked states
+    int hfirst = -1;                 // ... and this first H state
+    int shape = -1;                  // ... and these plane-pass shapes
+  } ig[2];
+  bool variances = true;             // mpe_iterate forms M = Psi^T Phi and the variances R^E
   hipEvent_t ev_in = nullptr;
   int64_t graph_launches = 0;
 
@@ -613,8 +618,9 @@ mpe_status enqueue_iterate(mpe_plan p, void* psi) {
   if (s == MPE_OK) s = run_h(p, p->phi, p->hphi, p->hfirst);
   const void* X[3] = {p->phi, p->phi, psi};
   const void* Y[3] = {p->phi, p->hphi, p->phi};
-  if (s == MPE_OK) s = run_gram(p, X, Y, 3, p->S(), 2);   // S, Hs (upper tiles), M contiguous
-  if (s == MPE_OK) {
+  // S, Hs (upper tiles) and, with the variances, M; contiguous
+  if (s == MPE_OK) s = run_gram(p, X, Y, p->variances ? 3 : 2, p->S(), 2);
+  if (s == MPE_OK && p->variances) {
     hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, p->re(), p->reperp(), p->st);
     if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));
   }
@@ -625,21 +631,21 @@ mpe_status enqueue_iterate(mpe_plan p, void* psi) {
   return MPE_OK;
 }
 
+void drop_graph_slot(mpe_plan_s::IterGraph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g = mpe_plan_s::IterGraph();
+}
+
 void drop_graph(mpe_plan p) {
-  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
-  p->gexec = nullptr;
-  p->graph = nullptr;
-  p->g_psi = nullptr;
-  p->g_spl = -1;
-  p->g_locked = -1;
-  p->g_hfirst = -1;
-  p->g_shape = -1;
+  drop_graph_slot(p->ig[0]);
+  drop_graph_slot(p->ig[1]);
 }
 
 // Capture enqueue_iterate(psi) on the private stream into an executable graph.
 mpe_status capture_iterate(mpe_plan p, void* psi) {
-  drop_graph(p);
+  mpe_plan_s::IterGraph& ig = p->ig[p->variances ? 1 : 0];
+  drop_graph_slot(ig);
   if (!p->gst) HIPCHK(p, hipStreamCreateWithFlags(&p->gst, hipStreamNonBlocking));
   if (!p->ev_in) HIPCHK(p, hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
   HIPCHK(p, hipStreamBeginCapture(p->gst, hipStreamCaptureModeRelaxed));
@@ -654,13 +660,13 @@ mpe_status capture_iterate(mpe_plan p, void* psi) {
     return s;
   }
   if (e != hipSuccess) return fail(p, MPE_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-  p->graph = g;
-  HIPCHK(p, hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
-  p->g_psi = psi;
-  p->g_spl = p->states_per_launch;
-  p->g_locked = p->locked;
-  p->g_hfirst = p->hfirst;
-  p->g_shape = p->shape_ver;
+  ig.graph = g;
+  HIPCHK(p, hipGraphInstantiate(&ig.exec, ig.graph, nullptr, nullptr, 0));
+  ig.psi = psi;
+  ig.spl = p->states_per_launch;
+  ig.locked = p->locked;
+  ig.hfirst = p->hfirst;
+  ig.shape = p->shape_ver;
   return MPE_OK;
 }
 
@@ -669,8 +675,15 @@ mpe_status finish_iterate(mpe_plan p, void* psi, double* eig, double* rh, double
   if (s != MPE_OK) return s;
   copy_out(eig, p->host_res, p->m);
   copy_out(rh, p->host_res + MAXM, p->m);
-  copy_out(re, p->host_res + 2 * MAXM, p->m);
-  copy_out(re_perp, p->host_res + 3 * MAXM, p->m);
+  if (p->variances) {
+    copy_out(re, p->host_res + 2 * MAXM, p->m);
+    copy_out(re_perp, p->host_res + 3 * MAXM, p->m);
+  } else {
+    for (int j = 0; j < p->m; ++j) {
+      if (re) re[j] = std::numeric_limits<double>::quiet_NaN();
+      if (re_perp) re_perp[j] = std::numeric_limits<double>::quiet_NaN();
+    }
+  }
   p->rr_cache_psi = psi;   // hphi now holds H psi (rotated)
   return MPE_OK;
 }
@@ -981,14 +994,15 @@ mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh
   if (s != MPE_OK) return s;
   p->last_dt = dt;
   if (p->use_graph && !p->prof) {
-    if (!p->gexec || p->g_psi != psi || p->g_spl != p->states_per_launch || p->g_shape != p->shape_ver ||
-        p->g_locked != p->locked || p->g_hfirst != p->hfirst) {
+    const mpe_plan_s::IterGraph& ig = p->ig[p->variances ? 1 : 0];
+    if (!ig.exec || ig.psi != psi || ig.spl != p->states_per_launch || ig.shape != p->shape_ver ||
+        ig.locked != p->locked || ig.hfirst != p->hfirst) {
       s = capture_iterate(p, psi);
       if (s != MPE_OK) return s;
     }
     HIPCHK(p, hipEventRecord(p->ev_in, p->st));           // tables and earlier work on the user stream
     HIPCHK(p, hipStreamWaitEvent(p->gst, p->ev_in, 0));
-    HIPCHK(p, hipGraphLaunch(p->gexec, p->gst));
+    HIPCHK(p, hipGraphLaunch(p->ig[p->variances ? 1 : 0].exec, p->gst));
     HIPCHK(p, hipStreamSynchronize(p->gst));
     p->graph_launches++;
   } else {
@@ -1019,6 +1033,12 @@ mpe_status mpe_set_graph(mpe_plan p, int32_t on) {
   if (!p) return MPE_ERR_INVALID_ARGUMENT;
   p->use_graph = on != 0;
   if (!p->use_graph) drop_graph(p);
+  return MPE_OK;
+}
+
+mpe_status mpe_set_variances(mpe_plan p, int32_t on) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  p->variances = on != 0;
   return MPE_OK;
 }
 

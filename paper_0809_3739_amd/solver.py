@@ -140,6 +140,11 @@ class Plan:
         iterations (selective propagation; see mpe_set_locked)."""
         self._check(self.lib.mpe_set_locked(self.h, int(locked)))
 
+    def set_variances(self, on: bool):
+        """Form R^E / R^E_perp in the following iterations (default) or skip them
+        (NaN outputs, one overlap product fewer); see mpe_set_variances."""
+        self._check(self.lib.mpe_set_variances(self.h, 1 if on else 0))
+
     @property
     def locked(self) -> int:
         return int(self.lib.mpe_get_locked(self.h))
@@ -283,7 +288,7 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
           n_check: int | None = None, margin: float = 0.01, max_iter_per_level: int = 2000,
           max_levels: int = 30, orthonormalize_first: bool = True, callback=None,
           stall_window: int | None = None, stall_gain: float = 0.02, accept=None,
-          lock_tol: float | None = None) -> SolveResult:
+          lock_tol: float | None = None, variance_every: int = 1) -> SolveResult:
     """Iterate with the protocol of Section III until R^H_j < gamma for the
     first ``n_check`` states.
 
@@ -311,6 +316,11 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
     iteration, so a locked state whose R^H rises again is released at once;
     locks are dropped when dt changes, and a level only ends on an iteration
     without locks, so its R^E test sees every state propagated.
+
+    With ``variance_every`` = k > 1 the variances are formed only in every k-th
+    iteration of a level (and in the iteration that confirms a level's end);
+    the others skip the overlap M = Psi^T Phi (``Plan.set_variances``) and
+    cannot end a level.
     """
     n_check = plan.n_states if n_check is None else n_check
     t0 = time.perf_counter()
@@ -328,13 +338,19 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
         return r
 
     plan.set_locked(0)
+    var_now = True
+    plan.set_variances(True)
     try:
         for level in range(max_levels):
             ge = margin * gamma * dt * dt
             rh_level = []
             plan.set_locked(0)
+            var_next = True
             for it in range(max_iter_per_level):
                 locked = plan.locked
+                if var_next != var_now:
+                    plan.set_variances(var_next)
+                    var_now = var_next
                 out = plan.iterate(psi, dt)
                 total += 1
                 props += plan.m - locked
@@ -357,6 +373,7 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
                     before = min(rh_level[:-stall_window])
                     if min(rh_level[-stall_window:]) > (1.0 - stall_gain) * before:
                         return result(out["eig"], out["rh"], level + 1, False, stalled=True)
+                confirm = False
                 if lock_tol is not None:
                     nl = 0
                     rh = out["rh"]
@@ -364,18 +381,22 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
                         nl += 1
                     if it > 0 and rep <= ge:
                         nl = 0   # the level may be done: confirm with every state propagated
+                        confirm = True
                     plan.set_locked(nl)
+                var_next = variance_every <= 1 or confirm or (it + 1) % variance_every == 0
             if float(np.max(out["rh"][:n_check])) < gamma:
                 return result(out["eig"], out["rh"], level + 1, True)
             dt *= reduce
         return result(out["eig"], out["rh"], max_levels, False)
     finally:
         plan.set_locked(0)
+        plan.set_variances(True)
 
 
 def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8,
                  stall_window: int = 20, check_below: float = 10.0, check_every: int = 10, callback=None,
-                 lock32: float | None = None, lock64: float | None = None, **kw) -> SolveResult:
+                 lock32: float | None = None, lock64: float | None = None, variance_every32: int = 10,
+                 **kw) -> SolveResult:
     """Float32 iterations until converged, then float64 only if needed.
 
     Float32 arithmetic puts a floor under the R^H it measures (the transforms'
@@ -389,7 +410,9 @@ def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0
     the same system; iterations and seconds of both stages are summed, and the
     result's ``psi`` is the float64 block.  ``lock32`` and ``lock64`` are the
     ``lock_tol`` of the two stages (selective propagation; None: every state
-    is propagated).
+    is propagated); ``variance_every32`` is the float32 stage's
+    ``variance_every`` (10: that stage ends by R^H, the float64 check or a
+    stall, so its variances are only needed for the rare level change).
     """
     t0 = time.perf_counter()
     n_check = kw.get("n_check") or plan32.n_states
@@ -409,7 +432,7 @@ def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0
         return None
 
     r1 = solve(plan32, psi32, dt0=dt0, gamma=gamma, stall_window=stall_window, callback=callback, accept=accept,
-               lock_tol=lock32, **kw)
+               lock_tol=lock32, variance_every=variance_every32, **kw)
     stages = [{"precision": "fp32", "iterations": r1.iterations, "seconds": round(r1.seconds, 3), "dt": r1.dt,
                "float64_checks": box.get("checks", 0), "max_rh": float(np.max(r1.rh[:n_check]))}]
     if r1.converged:

@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import re
 import math
 import os
 import time
@@ -178,8 +179,9 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
     random start is i.i.d. N(0, 1) from the geometry's seed.  A ``_lock<f>``
     suffix adds selective propagation: states are locked once their R^H is
     below ``f * gamma`` (f = 1 when omitted) in float32 and below ``gamma / 10``
-    in float64.  A final ``_g32`` runs the float32 stage's overlaps on float32
-    MFMA.
+    in float64.  ``_g32`` runs the float32 stage's overlaps on float32 MFMA, and
+    a final ``_v<k>`` forms the float32 stage's variances only every k-th
+    iteration (10 when omitted).
     """
     box = (BOX,) * 3
     p32 = solver.Plan((grid,) * 3, box, N_STATES, order, "fp32", n_guard=n_guard)
@@ -197,8 +199,13 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
         p64.set_potential(V)
         row = {"seed": int(s)}
         for var in variants:
-            g32 = var.endswith("_g32")
-            name = var[:-4] if g32 else var
+            name, ve = var, 10
+            mv = re.search(r"_v(\d+)$", name)
+            if mv:
+                ve = int(mv.group(1))
+                name = name[:mv.start()]
+            g32 = name.endswith("_g32")
+            name = name[:-4] if g32 else name
             base, _, lf = name.partition("_lock")
             lock = "_lock" in name
             p32.set_gemm_precision("fp32" if g32 else "fp64")
@@ -216,7 +223,7 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
             else:
                 q = start_quality(p32, psi)
                 r = solver.solve_ladder(p32, p64, psi, gamma=gamma, n_check=N_STATES, callback=progress,
-                                        lock32=lock32, lock64=lock64)
+                                        lock32=lock32, lock64=lock64, variance_every32=ve)
             torch.cuda.synchronize()
             secs = time.perf_counter() - t0
             row[var] = {"start_max_rh": q["max_rh"], "first_iteration_max_rh": r.history[0]["rh"],

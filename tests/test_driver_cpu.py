@@ -16,8 +16,10 @@ class ScriptedPlan:
         self.m, self.n_states = m, n_states
         self.script = list(script)      # per iteration: (rh array, re_perp array)
         self.locked_seen = []
+        self.var_seen = []
         self.dts = []
         self._locked = 0
+        self._var = True
 
     @property
     def locked(self):
@@ -27,13 +29,19 @@ class ScriptedPlan:
         assert 0 <= n <= self.m
         self._locked = n
 
+    def set_variances(self, on):
+        self._var = bool(on)
+
     def orthonormalize(self, psi):
         pass
 
     def iterate(self, psi, dt):
         self.locked_seen.append(self._locked)
+        self.var_seen.append(self._var)
         self.dts.append(dt)
         rh, rep = self.script.pop(0)
+        if not self._var:
+            rep = [float("nan")] * self.m
         return {"rh": np.asarray(rh, float), "re_perp": np.asarray(rep, float), "eig": np.arange(self.m, dtype=float),
                 "re": np.asarray(rep, float)}
 
@@ -98,3 +106,18 @@ def test_accept_hook_ends_the_solve(lock):
     r = solver.solve(plan, None, gamma=1e-10, lock_tol=lock,
                      accept=lambda out, it: {"eig": out["eig"], "rh": out["rh"]} if it == 3 else None)
     assert r.converged and r.iterations == 3
+
+
+def test_variances_every_k_iterations_and_for_the_confirming_one():
+    m = 3
+    far, part, done = ([1e-3] * m, [1.0] * m), ([1e-12, 1e-3, 1e-3], [1.0] * m), ([1e-12, 1e-3, 1e-3], [0.0] * m)
+    script = [far, part, part, done, done, ([1e-20] * m, [1.0] * m)]
+    plan = ScriptedPlan(m, 3, script)
+    r = solver.solve(plan, None, dt0=0.4, gamma=1e-10, lock_tol=1e-11, variance_every=3)
+    assert r.converged
+    # variances in iterations 0 and 3 by the period; 3 meets the R^E test with a lock in force, so 4
+    # confirms it unlocked and with variances; the level ends there and the next starts with them
+    assert plan.var_seen == [True, False, False, True, True, True]
+    assert plan.locked_seen == [0, 0, 1, 1, 0, 0]
+    assert plan.dts == [0.4] * 5 + [0.2]
+    assert plan._var is True        # restored at the end

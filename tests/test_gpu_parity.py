@@ -584,6 +584,33 @@ def test_locked_states_reuse_h_from_the_rotation(P):
         assert np.abs(Pa.T @ (Pa @ Pb.T) - Pb.T).max() < 1e-10
 
 
+def test_variances_off_changes_nothing_else(P):
+    """Iterations without the variances (mpe_set_variances off) return NaN R^E and
+    otherwise the same block, Ritz values and R^H bitwise, also when toggled
+    between graph replays (one captured graph per setting)."""
+    grid, box = (32, 32, 32), (12.0, 12.0, 12.0)
+    say("variances off")
+    V = toy_potential(grid, box)
+    psi0 = W.random_states(8, 8, grid)
+    runs = []
+    for graph, pattern in ((False, (True,) * 5), (True, (True, False, False, True, False))):
+        plan = P.Plan(grid, box, 8, 6, "fp64")
+        plan.set_potential(V)
+        plan.set_graph(graph)
+        psi = plan.new_states(psi0)
+        plan.orthonormalize(psi)
+        outs = []
+        for on in pattern:
+            plan.set_variances(on)
+            r = plan.iterate(psi, 0.3)
+            assert np.all(np.isfinite(r["re_perp"])) == on and (on or np.all(np.isnan(r["re_perp"])))
+            outs.append((psi.cpu().numpy().copy(), r["eig"].copy(), r["rh"].copy()))
+        runs.append(outs)
+    for a, b in zip(*runs):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
 def test_locked_bounds(P):
     grid, box = (16, 16, 16), (8.0, 8.0, 8.0)
     say("locked bounds")
