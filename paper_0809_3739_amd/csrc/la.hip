@@ -614,15 +614,20 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   // the rotations of every step are logged (flag, then (c, s) per pair) and the
   // eigenvectors are rebuilt from the log once the sweeps are done
   double* lg = d.rot;
-  // the 2x2 blocks (k, l) of this thread, fixed for every step (k = e / half, l = e % half)
-  constexpr int SD_BLOCKS = (MAXM / 2) * (MAXM / 2) / SD_THREADS;
+  // the 2x2 blocks (k, l), k <= l, of this thread, fixed for every step; A stays
+  // symmetric, so block (l, k) is written as the transpose of block (k, l)
+  constexpr int SD_BLOCKS = ((MAXM / 2) * (MAXM / 2 + 1) / 2 + SD_THREADS - 1) / SD_THREADS;
+  const int nbt = half * (half + 1) / 2;
   int blk_k[SD_BLOCKS], blk_l[SD_BLOCKS], nblk = 0;
 #pragma unroll
   for (int b = 0; b < SD_BLOCKS; ++b) {
-    const int e = tid + b * SD_THREADS;
-    blk_k[b] = e < half * half ? e / half : 0;
-    blk_l[b] = e < half * half ? e % half : 0;
-    if (e < half * half) nblk = b + 1;
+    const int e = tid + b * SD_THREADS;   // row-major index into the triangle l >= k
+    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    blk_l[b] = e < nbt ? i : 0;
+    blk_k[b] = e < nbt ? e - i * (i + 1) / 2 : 0;
+    if (e < nbt) nblk = b + 1;
   }
   int sweep = 0;
   bool converged = false;
@@ -688,10 +693,18 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
           const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
           const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
           // columns: J_l
-          A(pk, pl) = cl * r00 - sl * r01;
-          A(pk, ql) = sl * r00 + cl * r01;
-          A(qk, pl) = cl * r10 - sl * r11;
-          A(qk, ql) = sl * r10 + cl * r11;
+          const double n00 = cl * r00 - sl * r01, n01 = sl * r00 + cl * r01;
+          const double n10 = cl * r10 - sl * r11, n11 = sl * r10 + cl * r11;
+          A(pk, pl) = n00;
+          A(pk, ql) = n01;
+          A(qk, pl) = n10;
+          A(qk, ql) = n11;
+          if (k != l) {   // the mirrored block
+            A(pl, pk) = n00;
+            A(ql, pk) = n01;
+            A(pl, qk) = n10;
+            A(ql, qk) = n11;
+          }
         }
       }
       __syncthreads();
