@@ -324,6 +324,29 @@ def test_float32_gemms_solve_oscillator(P):
     assert err < 1e-6
 
 
+@pytest.mark.parametrize("locks", [(None, None), (3e-10, 1e-11)])
+def test_solve_ladder_oscillator(P, locks):
+    """The float32-then-float64 ladder (with and without selective propagation, float32
+    overlaps and sparse variances in the float32 stage) reaches R^H < gamma and the
+    exact oscillator levels; a float32 stage that meets gamma itself ends the solve with
+    float32 Ritz values, hence the float32 bar on the levels."""
+    s = W.harmonic_system(32, 16.0, 10)
+    say("solve ladder oscillator, locks", locks)
+    p32 = P.Plan(s.grid, s.box, 10, 4, "fp32", n_guard=2)
+    p64 = P.Plan(s.grid, s.box, 10, 4, "fp64", n_guard=2)
+    for p in (p32, p64):
+        p.set_potential(s.V)
+    p32.set_gemm_precision("fp32")
+    psi = p32.new_states(W.random_states(2, 12, s.grid))
+    r = P.solve_ladder(p32, p64, psi, dt0=0.1, gamma=1e-10, lock32=locks[0], lock64=locks[1])
+    exact = dense.separable_oscillator_levels(32, 16.0, 10)
+    err = np.max(np.abs(r.eig[:10] - exact) / exact)
+    say("  iterations", r.iterations, "propagations", r.propagations, "stages", r.stages, "eig rel err", err)
+    assert r.converged and err < 1e-6
+    assert float(np.max(r.rh[:10])) < 1e-10
+    assert p32.locked == 0 and p64.locked == 0
+
+
 def test_iterate_lockstep_oscillator(P):
     """Config-1 geometry: 32^3 oscillator, 10 states, order 4, dt = 0.1, float64, lockstep."""
     s = W.harmonic_system(32, 16.0, 10)
