@@ -13,6 +13,8 @@ order, half-spectrum handling, Nyquist, normalisation) shows up as a mismatch.
 * ``t2_dense`` / ``mpe_dense`` -- the split operator (Eq. so) and the
   multi-product expansion (Eq. mcomp) as explicit matrices, with exp(-tau T)
   from the eigen-decomposition of the 1-D kinetic matrices.
+* ``romberg6_dense`` -- the Romberg-type sixth-order operator of Eq. sixp as an
+  explicit matrix, its weights from an exact 2 x 2 solve.
 """
 from __future__ import annotations
 
@@ -121,6 +123,26 @@ def mpe_dense(V: np.ndarray, grid, box, dt: float, K: int, hbar2_over_m: float =
     for k in range(1, K + 1):
         out += w[k - 1] * np.linalg.matrix_power(t2_dense(V, grid, box, dt / k, hbar2_over_m), k)
     return out
+
+
+def romberg_weights(order: int) -> list:
+    """Weights (w_1, w_2) with w_1 + w_2 = 1 and w_1 + w_2 / 2^order = 0.
+
+    An integrator of order ``order`` has a one-step error C eps^(order+1); two
+    steps at eps/2 carry 2 C (eps/2)^(order+1) = C eps^(order+1) / 2^order, so
+    these weights cancel it (an exact rational 2 x 2 solve, independent of the
+    printed fractions of Eq. sixp)."""
+    r = Fraction(1, 2 ** order)
+    w2 = Fraction(1) / (1 - r)
+    return [1 - w2, w2]
+
+
+def romberg6_dense(V: np.ndarray, grid, box, dt: float, hbar2_over_m: float = 1.0) -> np.ndarray:
+    """Dense Romberg T6 = w_1 T4(dt) + w_2 T4(dt/2)^2 (Eq. sixp) with T4 the dense order-4 MPE matrix."""
+    w = [float(x) for x in romberg_weights(4)]
+    A = mpe_dense(V, grid, box, dt, 2, hbar2_over_m)
+    B = mpe_dense(V, grid, box, 0.5 * dt, 2, hbar2_over_m)
+    return w[0] * A + w[1] * (B @ B)
 
 
 def exact_propagator_dense(H: np.ndarray, dt: float) -> np.ndarray:

@@ -128,6 +128,26 @@ def mpe_apply(psi: np.ndarray, V: np.ndarray, dt: float, K: int, grid, box,
     return acc
 
 
+def romberg6_apply(psi: np.ndarray, V: np.ndarray, dt: float, grid, box,
+                   hbar2_over_m: float = 1.0) -> np.ndarray:
+    """Romberg-type sixth-order operator built from the fourth-order one (Section II, Eq. sixp).
+
+    T6(eps) = -T4(eps)/15 + 16 T4(eps/2)^2 / 15 with T4 the order-4 expansion
+    (Eq. four): one T4 step at dt and two successive T4 steps at dt/2, i.e.
+    nine T2 applications against six for the multi-product T6 (Eq. six).
+    """
+    psi = np.asarray(psi, dtype=np.float64)
+    full = mpe_apply(psi, V, dt, 2, grid, box, hbar2_over_m)
+    half = mpe_apply(psi, V, 0.5 * dt, 2, grid, box, hbar2_over_m)
+    half = mpe_apply(half, V, 0.5 * dt, 2, grid, box, hbar2_over_m)
+    return (-1.0 / 15.0) * full + (16.0 / 15.0) * half
+
+
+def romberg6_t2_count() -> int:
+    """T2 applications per state of one Romberg T6 step: three T4 steps of three each."""
+    return 3 * t2_count(2)
+
+
 def h_apply(psi: np.ndarray, V: np.ndarray, grid, box, hbar2_over_m: float = 1.0) -> np.ndarray:
     """H psi = -(hbar^2/2m) Lap psi + V psi with the Laplacian applied spectrally (Eq. Ham)."""
     psi = np.asarray(psi, dtype=np.float64)
@@ -215,16 +235,22 @@ class IterResult:
 
 
 def iterate(psi: np.ndarray, V: np.ndarray, dt: float, K: int, grid, box,
-            hbar2_over_m: float = 1.0, keep_phi: bool = False, locked: int = 0) -> IterResult:
+            hbar2_over_m: float = 1.0, keep_phi: bool = False, locked: int = 0,
+            romberg6: bool = False) -> IterResult:
     """One iteration: propagate (Eq. propstep with Eq. mcomp), orthonormalise (Eq. ortho),
     Rayleigh-Ritz, and the variances R^E and R^H (Section III).
 
     ``locked``: selective propagation (Section III, only states whose variance is
     still above the bound are propagated): the first ``locked`` states are taken
-    over unpropagated, phi_j = psi_j, before the orthonormalisation."""
+    over unpropagated, phi_j = psi_j, before the orthonormalisation.
+    ``romberg6``: propagate with the Romberg-type T6 of Eq. sixp instead of the
+    order-2K expansion (K is then ignored)."""
     phi = np.array(psi, dtype=np.float64, copy=True)
     if locked < len(psi):
-        phi[locked:] = mpe_apply(psi[locked:], V, dt, K, grid, box, hbar2_over_m)
+        if romberg6:
+            phi[locked:] = romberg6_apply(psi[locked:], V, dt, grid, box, hbar2_over_m)
+        else:
+            phi[locked:] = mpe_apply(psi[locked:], V, dt, K, grid, box, hbar2_over_m)
     re, re_perp, _ = residual_e(psi, phi)
     Psi, _, _ = cholesky_orthonormalize(phi)
     HPsi = h_apply(Psi, V, grid, box, hbar2_over_m)

@@ -316,3 +316,121 @@ def test_truncated_icosahedron_geometry():
     nb = (D < dmin * 1.0001).sum(axis=1)
     assert (nb == 3).all()          # every carbon has three nearest neighbours; 90 edges
     assert nb.sum() // 2 == 90
+
+
+# ------------------------------------------------------------------ variances on an unconverged block
+@pytest.mark.parametrize("K,locked", [(2, 0), (3, 2)])
+def test_iterate_variances_on_unconverged_block(K, locked):
+    """R^E_j and R^E_perp_j of one iteration (Section III) on a random orthonormal
+    block, far from convergence, against least-squares distances built from the
+    dense propagator matrix: R^E_j is the squared distance of T psi_j from the
+    line through psi_j, R^E_perp_j its squared distance from span(Psi).  A mix-up
+    of the incoming and the propagated block changes both."""
+    grid, box = (8, 8, 8), (8.0, 8.0, 8.0)
+    V = toy8(grid, box)
+    m, dt = 5, 0.3
+    Q0, _ = np.linalg.qr(W.random_states(33, m, grid).reshape(m, -1).T)
+    psi = Q0.T.reshape(m, *grid)
+    F = dense.mpe_dense(V, grid, box, dt, K) @ Q0
+    F[:, :locked] = Q0[:, :locked]
+    re_ref = np.array([np.sum((F[:, j] - Q0[:, [j]] @ np.linalg.lstsq(Q0[:, [j]], F[:, j], rcond=None)[0]) ** 2)
+                       for j in range(m)])
+    coef = np.linalg.lstsq(Q0, F, rcond=None)[0]
+    perp_ref = np.sum((F - Q0 @ coef) ** 2, axis=0)
+    r = mpe.iterate(psi, V, dt, K, grid, box, locked=locked)
+    assert re_ref[locked:].min() > 1e-6          # the block is far from an invariant subspace
+    np.testing.assert_allclose(r.re, re_ref, rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(r.re_perp, perp_ref, rtol=1e-10, atol=1e-14)
+    assert np.all(r.re_perp <= r.re * (1 + 1e-12) + 1e-15)
+
+
+# ------------------------------------------------------------------ Romberg-type T6 (Eq. sixp)
+def test_romberg6_weights_match_printed():
+    # Eq. sixp prints -1/15 and 16/15; the weights follow from cancelling T4's leading error
+    assert dense.romberg_weights(4) == [Fraction(-1, 15), Fraction(16, 15)]
+
+
+@pytest.mark.parametrize("grid,box", [((6, 8, 4), (6.0, 8.0, 5.0)), ((8, 8, 8), (8.0, 8.0, 8.0))])
+def test_romberg6_matches_dense(grid, box):
+    V = toy8(grid, box)
+    psi = W.random_states(7, 2, grid)
+    dt = 0.3
+    got = mpe.romberg6_apply(psi, V, dt, grid, box)
+    R = dense.romberg6_dense(V, grid, box, dt)
+    want = (R @ psi.reshape(2, -1).T).T.reshape(psi.shape)
+    np.testing.assert_allclose(got, want, atol=1e-12 * np.abs(want).max())
+    # a different operator from the multi-product T6 of the same order
+    assert np.abs(got - mpe.mpe_apply(psi, V, dt, 3, grid, box)).max() > 1e-8 * np.abs(want).max()
+
+
+def test_romberg6_local_error_order():
+    """Local error of one Romberg step (Eq. sixp) built on the order-4 expansion
+    (Eq. four) against exp(-dt H).  The expansion's error is not a pure odd-power
+    exponent: with T2(e) = exp(eH + e^3 A + ...), T4 = -T2(e)/3 + 4 T2(e/2)^2/3
+    keeps a term -e^6 A^2/8 from the second order of each exponential, which
+    halving the step does not cancel (-1/15 and 16/15 of it leave e^6 A^2/240).
+    So the Romberg combination has local error O(dt^6) -- fifth order -- while the
+    multi-product T6 of the same cost class has O(dt^7)."""
+    grid, box = (8, 8, 8), (16.0, 16.0, 16.0)
+    V = soft8(grid, box)
+    H = dense.hamiltonian_dense(V, grid, box)
+    psi = W.random_states(9, 1, grid)
+    err, err_mpe = [], []
+    for dt in (0.2, 0.1):
+        E = dense.exact_propagator_dense(H, dt) @ psi.ravel()
+        err.append(np.linalg.norm(mpe.romberg6_apply(psi, V, dt, grid, box).ravel() - E))
+        err_mpe.append(np.linalg.norm(mpe.mpe_apply(psi, V, dt, 3, grid, box).ravel() - E))
+    slope = math.log2(err[0] / err[1])
+    assert abs(slope - 6) < 0.3, (err, slope)
+    assert math.log2(err_mpe[0] / err_mpe[1]) > 6.4
+    assert err[1] > 3 * err_mpe[1]
+
+
+def test_romberg6_cost():
+    """Section II: going from order 4 to 6 the Romberg form triples the T2 count (3 -> 9)
+    while the expansion adds K + 1 = 3 (3 -> 6)."""
+    assert mpe.romberg6_t2_count() == 3 * mpe.t2_count(2) == 9
+    assert mpe.t2_count(3) - mpe.t2_count(2) == 3
+
+
+def test_iterate_with_romberg6_matches_dense_subspace():
+    grid, box = (8, 8, 8), (8.0, 8.0, 8.0)
+    V = toy8(grid, box)
+    m, dt = 4, 0.3
+    Q0, _ = np.linalg.qr(W.random_states(35, m, grid).reshape(m, -1).T)
+    psi = Q0.T.reshape(m, *grid)
+    B = dense.romberg6_dense(V, grid, box, dt) @ Q0
+    Qb, _ = np.linalg.qr(B)
+    want = np.linalg.eigvalsh(Qb.T @ dense.hamiltonian_dense(V, grid, box) @ Qb)
+    r = mpe.iterate(psi, V, dt, 3, grid, box, romberg6=True)
+    np.testing.assert_allclose(r.theta, want, rtol=1e-11, atol=1e-12)
+
+
+# ------------------------------------------------------------------ the paper's model inputs
+def test_plane_wave_states_are_orthonormal_kinetic_eigenstates():
+    """The plane-wave start (Section III, convergence figures): discretely orthonormal,
+    each an eigenvector of the dense spectral kinetic operator, and together the
+    lowest eigenvalues of that operator in order."""
+    grid, box = (8, 6, 10), (7.0, 5.0, 9.0)
+    n = 20
+    P = W.plane_wave_states(n, grid, box).reshape(n, -1)
+    assert np.abs(P @ P.T - np.eye(n)).max() < 1e-13
+    T = dense.hamiltonian_dense(np.zeros((10, 6, 8)), grid, box, hbar2_over_m=2.0)
+    TP = (T @ P.T).T
+    e = np.einsum("ij,ij->i", P, TP)
+    assert np.abs(TP - e[:, None] * P).max() < 1e-10
+    assert np.all(np.diff(e) >= -1e-12) and abs(e[0]) < 1e-12
+    np.testing.assert_allclose(e, np.linalg.eigvalsh(T)[:n], atol=1e-10)
+
+
+def test_sech_cage_potential():
+    grid, box = (32, 32, 32), (16.0, 16.0, 16.0)
+    c = W.truncated_icosahedron(3.0)
+    V = W.sech_wells(grid, box, c[:1], 2.0, 0.7)
+    Z, Y, X = W.mesh(grid, box)
+    r = np.sqrt((X - c[0, 0]) ** 2 + (Y - c[0, 1]) ** 2 + (Z - c[0, 2]) ** 2)
+    i = np.unravel_index(np.argmin(r), r.shape)
+    assert abs(V[i] + 2.0 / math.cosh(r[i] / 0.7)) < 1e-14
+    assert V.max() < 0 and V.min() >= -2.0
+    full = W.sech_cage_potential(grid, box, V0=1.0, d=0.5, radius=3.0)
+    assert full.shape == (32, 32, 32) and full.min() < -1.0    # neighbouring wells overlap at d = 0.5

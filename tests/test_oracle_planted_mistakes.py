@@ -61,8 +61,25 @@ def _mpe_wrong_substep(psi, V, dt, K, grid, box, hbar2_over_m=1.0):
 _REAL_ITERATE = mpe.iterate
 
 
-def _iterate_lock_off_by_one(psi, V, dt, K, grid, box, hbar2_over_m=1.0, keep_phi=False, locked=0):
-    return _REAL_ITERATE(psi, V, dt, K, grid, box, hbar2_over_m, keep_phi, locked + 1 if locked else 0)
+def _iterate_lock_off_by_one(psi, V, dt, K, grid, box, hbar2_over_m=1.0, keep_phi=False, locked=0, romberg6=False):
+    return _REAL_ITERATE(psi, V, dt, K, grid, box, hbar2_over_m, keep_phi, locked + 1 if locked else 0, romberg6)
+
+
+def _iterate_variances_swapped(psi, V, dt, K, grid, box, hbar2_over_m=1.0, keep_phi=False, locked=0,
+                              romberg6=False):
+    r = _REAL_ITERATE(psi, V, dt, K, grid, box, hbar2_over_m, True, locked, romberg6)
+    re, re_perp, _ = mpe.residual_e(r.phi, psi)     # propagated block in place of the incoming one
+    r.re, r.re_perp = re, re_perp
+    return r
+
+
+_REAL_MPE_APPLY = mpe.mpe_apply
+
+
+def _romberg_half_step_once(psi, V, dt, grid, box, hbar2_over_m=1.0):
+    full = _REAL_MPE_APPLY(psi, V, dt, 2, grid, box, hbar2_over_m)
+    half = _REAL_MPE_APPLY(psi, V, 0.5 * dt, 2, grid, box, hbar2_over_m)   # T4(eps/2) once, not squared
+    return (-1.0 / 15.0) * full + (16.0 / 15.0) * half
 
 
 CASES = [
@@ -78,6 +95,10 @@ CASES = [
      [(pins.test_mpe_apply_matches_dense_expansion, (2,))]),
     ("one state too many left unpropagated", "iterate", _iterate_lock_off_by_one,
      [(pins.test_locked_iteration_matches_dense_subspace, (2,))]),
+    ("R^E formed with the propagated and incoming blocks exchanged", "iterate", _iterate_variances_swapped,
+     [(pins.test_iterate_variances_on_unconverged_block, (2, 0))]),
+    ("Romberg T6 with one half step instead of two", "romberg6_apply", _romberg_half_step_once,
+     [(pins.test_romberg6_matches_dense, ((6, 8, 4), (6.0, 8.0, 5.0))), (pins.test_romberg6_local_error_order, ())]),
 ]
 
 

@@ -15,10 +15,10 @@ Workloads (restated as seeded recipes, no external data):
 * the "C60-like" Gaussian-well cage: 60 wells of depth ``V0`` and width ``sigma``
   centred on the vertices of a truncated icosahedron of radius ``R``;
 * random molecules of Gaussian wells for the batched uneven workload;
-* jittered C60-like cages for the warm-start data set.
-
-The paper's own model (Section "Quantum well model of C60") uses sech wells of an
-unspecified geometry; the Gaussian-well cage stands in for it.
+* jittered C60-like cages for the warm-start data set;
+* the paper's own cage model (Section "Quantum well model of C60"): sech wells
+  -V0/cosh(|r - R_i|/d) on the same truncated-icosahedron vertices;
+* plane-wave starting states (the start of the paper's convergence figures).
 """
 from __future__ import annotations
 
@@ -92,6 +92,29 @@ def gaussian_wells(grid, box, centers, depths, sigmas) -> np.ndarray:
     return V
 
 
+def sech_wells(grid, box, centers, V0: float, d: float) -> np.ndarray:
+    """V(r) = -sum_i V0 / cosh(|r - R_i| / d), float64 [z][y][x] (the paper's cage model).
+
+    Wells are summed directly (no periodic images)."""
+    Z, Y, X = mesh(grid, box)
+    V = np.zeros(X.shape, dtype=np.float64)
+    for cx, cy, cz in np.asarray(centers, dtype=np.float64).reshape(-1, 3):
+        r = np.sqrt((X - cx) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2)
+        V -= V0 / np.cosh(r / d)
+    return V
+
+
+def sech_cage_potential(grid, box=(32.0, 32.0, 32.0), V0: float = 1.0, d: float = 0.05,
+                        radius: float = 6.7) -> np.ndarray:
+    """The paper's cage model: sech wells on the 60 truncated-icosahedron vertices.
+
+    The paper prints V0 = 1 (in units of hbar^2/2m) and d = 0.05 a.u. but no cage
+    radius, box or grid; the defaults here take the 6.7-bohr radius of the
+    Gaussian cage and its 32-bohr box.  In these units the Hamiltonian is
+    -Lap + V, i.e. hbar^2/m = 2 for the solver."""
+    return sech_wells(grid, box, truncated_icosahedron(radius), V0, d)
+
+
 def c60_like_potential(grid, box=(32.0, 32.0, 32.0), V0: float = 1.2, sigma: float = 0.9,
                        radius: float = 6.7, centers=None) -> np.ndarray:
     """Gaussian-well C60-like cage (60 wells on a truncated icosahedron), float64."""
@@ -105,6 +128,46 @@ def random_states(seed: int, count: int, grid) -> np.ndarray:
     """i.i.d. N(0,1) starting states, float64 [count][nz][ny][nx] (numpy default_rng)."""
     nx, ny, nz = (int(g) for g in grid)
     return np.random.default_rng(seed).standard_normal((count, nz, ny, nx))
+
+
+def plane_wave_states(count: int, grid, box) -> np.ndarray:
+    """The ``count`` lowest real plane waves of the periodic box, float64 [count][nz][ny][nx].
+
+    Wave vectors q = 2 pi (mx/Lx, my/Ly, mz/Lz) are taken in order of increasing
+    |q|^2 (ties broken by the integer vector), one of each pair +-m, giving the
+    constant state and then cos(q.r) and sin(q.r) per pair; Nyquist components
+    are skipped (their sine vanishes on the grid).  Each state is normalised
+    discretely: sum over grid points of psi^2 = 1."""
+    nx, ny, nz = (int(g) for g in grid)
+    Lx, Ly, Lz = (float(b) for b in box)
+    Z, Y, X = mesh(grid, box)
+    N = nx * ny * nz
+    lim = [n // 2 - 1 for n in (nx, ny, nz)]
+    reps = []
+    for mx in range(-lim[0], lim[0] + 1):
+        for my in range(-lim[1], lim[1] + 1):
+            for mz in range(-lim[2], lim[2] + 1):
+                m = (mx, my, mz)
+                first = next((t for t in m if t != 0), 0)
+                if first < 0:
+                    continue            # keep one of each pair +-m
+                q2 = (mx / Lx) ** 2 + (my / Ly) ** 2 + (mz / Lz) ** 2
+                reps.append((q2, m))
+    reps.sort()
+    out = []
+    for q2, (mx, my, mz) in reps:
+        if len(out) >= count:
+            break
+        if (mx, my, mz) == (0, 0, 0):
+            out.append(np.full(X.shape, 1.0 / math.sqrt(N)))
+            continue
+        ph = 2.0 * math.pi * (mx * (X + 0.5 * Lx) / Lx + my * (Y + 0.5 * Ly) / Ly + mz * (Z + 0.5 * Lz) / Lz)
+        out.append(math.sqrt(2.0 / N) * np.cos(ph))
+        if len(out) < count:
+            out.append(math.sqrt(2.0 / N) * np.sin(ph))
+    if len(out) < count:
+        raise ValueError("grid too small for that many plane waves")
+    return np.stack(out)
 
 
 # ----------------------------------------------------------------------------- workloads
