@@ -65,8 +65,10 @@ const char* mpe_status_string(mpe_status s);
 mpe_status mpe_coefficients(int32_t order, double* c);
 
 /* Create a plan (Introduction, problem statement; Section II for `order`).
- *  grid[3]  = (nx, ny, nz); supported: nx == ny in {8,16,32,48,64,96,128,192}
- *             (192 for MPE_FP32 only), nz in the same set.  Others: UNSUPPORTED.
+ *  grid[3]  = (nx, ny, nz); each in {8,16,32,48,64,96,128,192}.  Grids with
+ *             nx == ny run two passes per transform (x and y planes in one)
+ *             except float64 planes of 192 points, which like every grid with
+ *             nx != ny run three (see mpe_set_three_pass).  Others: UNSUPPORTED.
  *  box[3]   = (Lx, Ly, Lz) > 0, periodic box lengths.
  *  n_states = states whose convergence is checked; n_guard extra states carried
  *             along (m = n_states + n_guard <= 128 and m <= nx*ny*nz).
@@ -123,6 +125,13 @@ mpe_status mpe_rayleigh_ritz(mpe_plan p, void* psi, double* eig);
  * rh: host, m doubles (required). */
 mpe_status mpe_residuals(mpe_plan p, const void* psi, const double* eig, double* rh, double* re);
 
+/* Drop the H psi kept by the last mpe_rayleigh_ritz / mpe_iterate (see above
+ * and mpe_set_locked).  The library recognises the block only by its device
+ * address, so a caller that writes the block itself (or frees it and lets the
+ * address be reused) must call this before the next mpe_residuals or locked
+ * mpe_iterate; they then apply H afresh.  Always MPE_OK for a valid plan. */
+mpe_status mpe_forget_cached_h(mpe_plan p);
+
 /* One fused iteration (Section I, Eqs. propstep and ortho; Section III):
  *   Phi = T_order(dt) psi; H Phi; S = Phi Phi^T, Hs = Phi (H Phi)^T,
  *   M = psi Phi^T; generalised eigenproblem Hs c = theta S c by Cholesky and
@@ -176,6 +185,36 @@ mpe_status mpe_set_locked(mpe_plan p, int32_t locked);
  * products in the other iterations. */
 mpe_status mpe_set_variances(mpe_plan p, int32_t on);
 
+/* Propagator of mpe_step / mpe_iterate / mpe_residuals (Section II).
+ * MPE_PROP_EXPANSION (default): the order-2K multi-product expansion of the
+ * plan, K(K+1)/2 T2 applications per state.  MPE_PROP_ROMBERG6 (order-4 plans
+ * only, else MPE_ERR_UNSUPPORTED): the Romberg-type operator of Eq. sixp built
+ * from the order-4 expansion T4,
+ *   T(dt) = -T4(dt)/15 + 16 T4(dt/2)^2 / 15,
+ * nine T2 applications per state; the two terms are staged in two extra state
+ * blocks and combined in float64 with one rounding.  (Built on the expansion
+ * T4, whose error is not an odd-power exponent, this combination has local
+ * error O(dt^6), one order short of the expansion's T6.)  The first switch to
+ * MPE_PROP_ROMBERG6 allocates the dt/2 tables and 2 m N staging values
+ * (MPE_ERR_OUT_OF_MEMORY on failure).  MPE_ERR_INVALID_ARGUMENT for another kind. */
+enum { MPE_PROP_EXPANSION = 0, MPE_PROP_ROMBERG6 = 1 };
+mpe_status mpe_set_propagator(mpe_plan p, int32_t kind);
+/* Current propagator kind (-1 for a null plan). */
+int32_t mpe_get_propagator(mpe_plan p);
+
+/* Pass structure of the transforms.  The default two-pass form transforms a
+ * whole z plane (x and y) in one pass and z pencils in the other; it needs
+ * nx == ny and a plane that fits the LDS.  The three-pass form (x rows, y
+ * columns and z pencils as separate passes, more HBM traffic) serves every
+ * other grid and is chosen at plan creation when the plane does not fit;
+ * on != 0 forces it for any grid with row and column passes (the chain output
+ * buffers are then allocated, MPE_ERR_OUT_OF_MEMORY on failure), on == 0
+ * returns to two passes where they are possible (else MPE_ERR_UNSUPPORTED).
+ * Both forms compute the same transforms; results agree to rounding. */
+mpe_status mpe_set_three_pass(mpe_plan p, int32_t on);
+/* 1 for a three-pass plan, 0 for two passes, -1 for a null plan. */
+int32_t mpe_get_three_pass(mpe_plan p);
+
 /* Current number of locked states (-1 for a null plan). */
 int32_t mpe_get_locked(mpe_plan p);
 
@@ -183,15 +222,18 @@ int32_t mpe_get_locked(mpe_plan p);
 mpe_status mpe_set_states_per_launch(mpe_plan p, int32_t states);
 
 /* Launch shape of the forward (kernel_class MPE_KC_PLANE_FWD) or link
- * (MPE_KC_PLANE_LINK) plane passes, for grids with nx >= 64 (smaller grids
- * always use mode 0):
- *   mode 0: one work-group per (z, state) plane (the default);
- *   mode 1: blocks_per_cu work-groups per CU loop over the planes, each
- *           loading the next plane's input while it transforms the current
- *           one, compiled with the register budget of one work-group per CU;
- *   mode 2: the same loop at the register budget of mode 0.
+ * (MPE_KC_PLANE_LINK) plane passes.  mode = persistence + 3 * order:
+ *   persistence 0: one work-group per (z, state) plane (the default);
+ *   persistence 1: blocks_per_cu work-groups per CU loop over the planes, each
+ *                  loading the next plane's input while it transforms the
+ *                  current one, compiled with the register budget of one
+ *                  work-group per CU (grids with nx >= 64; smaller grids fall
+ *                  back to persistence 0);
+ *   persistence 2: the same loop at the register budget of persistence 0;
+ *   order 0: z planes fastest; order 1: states fastest (the work-groups in
+ *            flight share a few z planes of the potential-factor table).
  * Results are bitwise identical for every shape.  MPE_ERR_INVALID_ARGUMENT
- * for another class, a mode outside 0..2 or blocks_per_cu outside 1..16
+ * for another class, a mode outside 0..5 or blocks_per_cu outside 1..16
  * (persistent modes). */
 mpe_status mpe_set_plane_shape(mpe_plan p, int32_t kernel_class, int32_t mode, int32_t blocks_per_cu);
 
@@ -216,7 +258,8 @@ mpe_status mpe_set_gemm_precision(mpe_plan p, int32_t mode);
 mpe_status mpe_get_plane_shape(mpe_plan p, int32_t* shape);
 
 /* Autotuner: times the candidate plane shapes (mode, blocks per CU) in
- * {(0,0), (1,1), (2,1), (2,2), (2,4)} on `reps` steps of psi (read only; the
+ * {(0,0), (1,1), (2,1), (2,2), (2,4)} and the same five with states fastest
+ * (modes 3..5) on `reps` steps of psi (read only; the
  * steps write the plan's workspace) at dt, and keeps the fastest shape per
  * pass.  With cache_path (may be NULL), a line "key|fwd_mode fwd_bpc
  * link_mode link_bpc" keyed by device, CU count, grid, precision, block size

@@ -48,10 +48,15 @@ SIGNATURES = {
     "mpe_rayleigh_ritz": (C.c_int, [_vp, _vp, _dp]),
     "mpe_residuals": (C.c_int, [_vp, _vp, _dp, _dp, _dp]),
     "mpe_iterate": (C.c_int, [_vp, _vp, C.c_double, _dp, _dp, _dp, _dp]),
+    "mpe_forget_cached_h": (C.c_int, [_vp]),
     "mpe_set_states_per_launch": (C.c_int, [_vp, _i32]),
     "mpe_set_locked": (C.c_int, [_vp, _i32]),
     "mpe_set_variances": (C.c_int, [_vp, _i32]),
     "mpe_get_locked": (_i32, [_vp]),
+    "mpe_set_propagator": (C.c_int, [_vp, _i32]),
+    "mpe_set_three_pass": (C.c_int, [_vp, _i32]),
+    "mpe_get_three_pass": (_i32, [_vp]),
+    "mpe_get_propagator": (_i32, [_vp]),
     "mpe_set_plane_shape": (C.c_int, [_vp, _i32, _i32, _i32]),
     "mpe_get_plane_shape": (C.c_int, [_vp, C.POINTER(_i32)]),
     "mpe_set_gemm_precision": (C.c_int, [_vp, _i32]),

@@ -134,12 +134,18 @@ struct mpe_plan_s {
   void* W = nullptr;           // K chains x m states x spec complex
   void* tailbuf = nullptr;     // split tail: K chains x m states x N real (when tail_split)
   bool split_tail = false;
+  bool three_pass = false;     // x rows, y columns and z pencils as separate passes
   void* phi = nullptr;         // m x N
   void* hphi = nullptr;        // m x N
   double* V64 = nullptr;       // N
   void* Vf = nullptr;          // N, data type
   void* fac = nullptr;         // 2K x N
   void* kin = nullptr;         // K x (nxh+ny+nz)
+  // Romberg propagator (mpe_set_propagator): tables at dt/2 and two staging blocks
+  int prop = MPE_PROP_EXPANSION;
+  void* fac2 = nullptr;        // 2K x N at dt/2
+  void* kin2 = nullptr;        // K x (nxh+ny+nz) at dt/2
+  void* rtmp = nullptr;        // 2 x m x N: T4(dt) psi | T4(dt/2)^2 psi
   void* hk = nullptr;          // nxh+ny+nz
   void* roots = nullptr;       // rx | ry | rz | wpost
   size_t off_ry = 0, off_rz = 0, off_wp = 0;
@@ -271,22 +277,26 @@ void collect_times(mpe_plan p) {
 }
 
 template <typename F>
-hipError_t launch_factor_tables(mpe_plan p, double dt) {
+hipError_t launch_factor_tables(mpe_plan p, double dt, void* fac, void* kin) {
   const long N = p->N;
   hipLaunchKernelGGL(factor_tables_kernel<F>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, p->st, p->V64, N, dt,
-                     2 * p->K, reinterpret_cast<F*>(p->fac));
+                     2 * p->K, reinterpret_cast<F*>(fac));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int len = p->nxh + p->ny + p->nz;
   hipLaunchKernelGGL(kinetic_tables_kernel<F>, dim3((len + 255) / 256), dim3(256), 0, p->st, p->nx, p->ny, p->nz, p->Lx,
-                     p->Ly, p->Lz, p->h2m, dt, p->K, reinterpret_cast<F*>(p->kin), reinterpret_cast<F*>(p->hk));
+                     p->Ly, p->Lz, p->h2m, dt, p->K, reinterpret_cast<F*>(kin), reinterpret_cast<F*>(p->hk));
   return hipGetLastError();
 }
 
 mpe_status ensure_tables(mpe_plan p, double dt) {
   if (!p->have_v) return fail(p, MPE_ERR_STATE, "no potential set (mpe_set_potential)");
   if (p->tab_dt == dt) return MPE_OK;
-  HIPCHK(p, p->dbl ? launch_factor_tables<double>(p, dt) : launch_factor_tables<float>(p, dt));
+  HIPCHK(p, p->dbl ? launch_factor_tables<double>(p, dt, p->fac, p->kin)
+                   : launch_factor_tables<float>(p, dt, p->fac, p->kin));
+  if (p->prop == MPE_PROP_ROMBERG6)   // the two half steps of Eq. sixp
+    HIPCHK(p, p->dbl ? launch_factor_tables<double>(p, 0.5 * dt, p->fac2, p->kin2)
+                     : launch_factor_tables<float>(p, 0.5 * dt, p->fac2, p->kin2));
   p->tab_dt = dt;
   return MPE_OK;
 }
@@ -332,10 +342,16 @@ void* chain_spec(mpe_plan p, int k) {  // k = 0..K-1
   return (char*)p->W + (size_t)k * p->m * p->spec * p->cx_size();
 }
 
+mpe_status enqueue_step3(mpe_plan p, const void* src, void* dst, int first, const void* fac, const void* kin);
+
 // dst <- T_2K(dt) src, all m states (src may equal dst); tables for dt must be current.
 // Propagation of states [first, m) of src into dst (the rows below first are
 // not touched).
-mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0) {
+mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0, const void* fac = nullptr,
+                        const void* kin = nullptr) {
+  if (!fac) fac = p->fac;
+  if (!kin) kin = p->kin;
+  if (p->three_pass) return enqueue_step3(p, src, dst, first, fac, kin);
   const size_t f = p->fsz;
   double c[MAX_K];
   mpe_coeffs(p->K, c);
@@ -343,17 +359,18 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0) {
     void* Wk = chain_spec(p, k - 1);
     const int half = 2 * k - 1;   // table exp(-dt V / 2k)
     const int full = k - 1;       // table exp(-dt V / k)
-    const void* ktab = (const char*)p->kin + (size_t)(k - 1) * (p->nxh + p->ny + p->nz) * f;
+    const void* ktab = (const char*)kin + (size_t)(k - 1) * (p->nxh + p->ny + p->nz) * f;
     Timer t;
     tic(p, t, MPE_KC_PLANE_FWD);
     HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
              PlaneArgs a = plane_base(p);
              a.real_in = src;
-             a.fac = p->fac;
+             a.fac = fac;
              a.fac_index = half;
              a.spec = Wk;
              a.state0 = s0;
-             a.persist_mode = p->pmode[0];
+             a.persist_mode = p->pmode[0] % 3;
+             a.states_fast = p->pmode[0] / 3;
              a.persist_blocks = p->pbpc[0] * p->n_cu;
              return launch_plane(p->dbl, PM_FWD, p->nx, a, p->nz, cnt, p->st);
            }, first));
@@ -371,10 +388,11 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0) {
         HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
                  PlaneArgs a = plane_base(p);
                  a.spec = Wk;
-                 a.fac = p->fac;
+                 a.fac = fac;
                  a.fac_index = full;
                  a.state0 = s0;
-                 a.persist_mode = p->pmode[1];
+                 a.persist_mode = p->pmode[1] % 3;
+                 a.states_fast = p->pmode[1] / 3;
                  a.persist_blocks = p->pbpc[1] * p->n_cu;
                  return launch_plane(p->dbl, PM_LINK, p->nx, a, p->nz, cnt, p->st);
                }, first));
@@ -391,7 +409,7 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0) {
       HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
                PlaneArgs a = plane_base(p);
                a.spec = chain_spec(p, k);
-               a.fac = p->fac;
+               a.fac = fac;
                a.fac_index = 2 * k + 1;
                a.real_out = out_k;
                a.state0 = s0;
@@ -406,7 +424,7 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0) {
              PlaneArgs a = plane_base(p);
              a.spec = chain_spec(p, 0);
              a.chain_stride = (long)p->m * p->spec;
-             a.fac = p->fac;
+             a.fac = fac;
              a.real_out = dst;
              a.K = p->K;
              for (int k = 0; k < p->K; ++k) a.coef[k] = c[k];
@@ -418,10 +436,107 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0) {
   return MPE_OK;
 }
 
+// y transforms of every z plane of states [s0, s0 + cnt): the pencil kernel
+// along y (stride NX/2+1), one "state" per (state, z) plane.
+hipError_t launch_ypass(mpe_plan p, int kind, void* spec, int s0, int cnt) {
+  PencilArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.data = spec;
+  a.rz = p->ry();
+  a.state_stride = (long)p->ny * p->nxh;
+  a.M = p->nxh;
+  a.NXH = p->nxh;
+  a.NY = p->ny;
+  a.state0 = s0 * p->nz;
+  return launch_pencil(p->dbl, kind, p->ny, a, cnt * p->nz, p->st);
+}
+
+PlaneArgs row_base(mpe_plan p, void* spec, const void* fac, int fac_index, int s0) {
+  PlaneArgs a = plane_base(p);
+  a.spec = spec;
+  a.fac = fac;
+  a.fac_index = fac_index;
+  a.state0 = s0;
+  return a;
+}
+
+// Three-pass form of enqueue_step: per T2 application a z pencil pass and
+// row / column passes in place of the plane pass; each chain leaves through a
+// row pass into its real buffer, combined in float64.
+mpe_status enqueue_step3(mpe_plan p, const void* src, void* dst, int first, const void* fac, const void* kin) {
+  const size_t f = p->fsz;
+  double c[MAX_K];
+  mpe_coeffs(p->K, c);
+  for (int k = 1; k <= p->K; ++k) {
+    void* Wk = chain_spec(p, k - 1);
+    const void* ktab = (const char*)kin + (size_t)(k - 1) * (p->nxh + p->ny + p->nz) * f;
+    void* out_k = (char*)p->tailbuf + (size_t)(k - 1) * p->m * p->N * f;
+    Timer t;
+    tic(p, t, MPE_KC_PLANE_FWD);
+    HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
+             PlaneArgs a = row_base(p, Wk, fac, 2 * k - 1, s0);
+             a.real_in = src;
+             hipError_t e = launch_rows(p->dbl, RW_FWD, p->nx, a, p->ny, p->nz, cnt, p->st);
+             return e == hipSuccess ? launch_ypass(p, PK_FFT_FWD, Wk, s0, cnt) : e;
+           }, first));
+    toc(p, t);
+    for (int l = 1; l <= k; ++l) {
+      tic(p, t, MPE_KC_PENCIL);
+      HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
+               PencilArgs a = pencil_base(p, Wk, ktab);
+               a.state0 = s0;
+               return launch_pencil(p->dbl, PK_EXP, p->nz, a, cnt, p->st);
+             }, first));
+      toc(p, t);
+      tic(p, t, l < k ? MPE_KC_PLANE_LINK : MPE_KC_PLANE_TAIL);
+      HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
+               hipError_t e = launch_ypass(p, PK_FFT_INV, Wk, s0, cnt);
+               if (e != hipSuccess) return e;
+               if (l < k) {
+                 PlaneArgs a = row_base(p, Wk, fac, k - 1, s0);
+                 e = launch_rows(p->dbl, RW_LINK, p->nx, a, p->ny, p->nz, cnt, p->st);
+                 return e == hipSuccess ? launch_ypass(p, PK_FFT_FWD, Wk, s0, cnt) : e;
+               }
+               PlaneArgs a = row_base(p, Wk, fac, 2 * k - 1, s0);
+               a.real_out = out_k;
+               return launch_rows(p->dbl, RW_OUT, p->nx, a, p->ny, p->nz, cnt, p->st);
+             }, first));
+      toc(p, t);
+    }
+  }
+  Timer t;
+  tic(p, t, MPE_KC_PLANE_TAIL);
+  const size_t off = (size_t)first * p->N * f;
+  HIPCHK(p, launch_combine(p->dbl, (const char*)p->tailbuf + off, (long)p->m * p->N, p->K, c, (char*)dst + off,
+                           (long)(p->m - first) * p->N, p->st));
+  toc(p, t);
+  return MPE_OK;
+}
+
+// dst <- T(dt) src for states [first, m) with the plan's propagator: the
+// order-2K expansion, or the Romberg-type T6 of Section II (Eq. sixp) built
+// from the order-4 expansion T4 (K = 2): -T4(dt)/15 + 16 T4(dt/2)^2/15, the
+// two terms staged in rtmp and combined in float64 with one rounding.
+mpe_status enqueue_propagate(mpe_plan p, const void* src, void* dst, int first = 0) {
+  if (p->prop != MPE_PROP_ROMBERG6) return enqueue_step(p, src, dst, first);
+  const size_t blk = (size_t)p->m * p->N;
+  void* full = p->rtmp;
+  void* half = (char*)p->rtmp + blk * p->fsz;
+  mpe_status s = enqueue_step(p, src, full, first);
+  if (s == MPE_OK) s = enqueue_step(p, src, half, first, p->fac2, p->kin2);
+  if (s == MPE_OK) s = enqueue_step(p, half, half, first, p->fac2, p->kin2);
+  if (s != MPE_OK) return s;
+  const double w[2] = {-1.0 / 15.0, 16.0 / 15.0};
+  const size_t off = (size_t)first * p->N * p->fsz;
+  HIPCHK(p, launch_combine(p->dbl, (const char*)p->rtmp + off, (long)blk, 2, w, (char*)dst + off,
+                           (long)(p->m - first) * p->N, p->st));
+  return MPE_OK;
+}
+
 mpe_status run_step(mpe_plan p, const void* src, void* dst, double dt) {
   mpe_status s = ensure_tables(p, dt);
   if (s != MPE_OK) return s;
-  s = enqueue_step(p, src, dst);
+  s = enqueue_propagate(p, src, dst);
   if (s == MPE_OK) p->last_dt = dt;
   return s;
 }
@@ -436,6 +551,26 @@ mpe_status run_h(mpe_plan p, const void* src, void* hdst, int first = 0) {
   void* Wh = chain_spec(p, 0);
   Timer t;
   tic(p, t, MPE_KC_H_APPLY);
+  if (p->three_pass) {
+    HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
+             PlaneArgs a = row_base(p, Wh, nullptr, -1, s0);
+             a.real_in = src;
+             hipError_t e = launch_rows(p->dbl, RW_FWD, p->nx, a, p->ny, p->nz, cnt, p->st);
+             if (e == hipSuccess) e = launch_ypass(p, PK_FFT_FWD, Wh, s0, cnt);
+             if (e != hipSuccess) return e;
+             PencilArgs b = pencil_base(p, Wh, p->hk);
+             b.state0 = s0;
+             e = launch_pencil(p->dbl, PK_ADD, p->nz, b, cnt, p->st);
+             if (e == hipSuccess) e = launch_ypass(p, PK_FFT_INV, Wh, s0, cnt);
+             if (e != hipSuccess) return e;
+             PlaneArgs c = row_base(p, Wh, p->Vf, -1, s0);
+             c.real_in = src;
+             c.real_out = hdst;
+             return launch_rows(p->dbl, RW_HTAIL, p->nx, c, p->ny, p->nz, cnt, p->st);
+           }, first));
+    toc(p, t);
+    return MPE_OK;
+  }
   HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
            PlaneArgs a = plane_base(p);
            a.real_in = src;
@@ -461,23 +596,9 @@ mpe_status run_h(mpe_plan p, const void* src, void* hdst, int first = 0) {
   return MPE_OK;
 }
 
-int gram_chunks(mpe_plan p, long* chunk) {
-  long nch = std::min<long>(256, std::max<long>(1, (p->N + 4095) / 4096));
-  long c = (p->N + nch - 1) / nch;
-  c = (c + 15) / 16 * 16;
-  nch = (p->N + c - 1) / c;
-  *chunk = c;
-  return (int)nch;
-}
+int gram_chunks(mpe_plan p, long* chunk) { return gram_chunking(p->N, 256, chunk); }
 
-int rot_chunks(mpe_plan p, long* chunk) {
-  long nch = std::min<long>(1024, std::max<long>(1, (p->N + 255) / 256));
-  long c = (p->N + nch - 1) / nch;
-  c = (c + 63) / 64 * 64;
-  nch = (p->N + c - 1) / c;
-  *chunk = c;
-  return (int)nch;
-}
+int rot_chunks(mpe_plan p, long* chunk) { return rot_chunking(p->N, chunk); }
 
 // Overlaps X_i Y_i^T (i < nprod) reduced into outs[i] (mp x mp float64 each, contiguous from out0).
 mpe_status run_gram(mpe_plan p, const void* const* X, const void* const* Y, int nprod, double* out0,
@@ -612,7 +733,7 @@ mpe_status enqueue_iterate(mpe_plan p, void* psi) {
   // locked states (Section III: only states not yet converged need propagating)
   // enter the overlaps and the rotation unpropagated: Phi_j = Psi_j
   if (p->locked > 0) HIPCHK(p, launch_copy16(p->phi, psi, (size_t)p->locked * p->N * p->fsz, p->st));
-  mpe_status s = enqueue_step(p, psi, p->phi, p->locked);
+  mpe_status s = enqueue_propagate(p, psi, p->phi, p->locked);
   // H Phi_j = H Psi_j of the locked states is still in hphi from the previous
   // rotation when nothing touched psi since (p->hfirst > 0 only then)
   if (s == MPE_OK) s = run_h(p, p->phi, p->hphi, p->hfirst);
@@ -727,7 +848,7 @@ mpe_status mpe_plan_destroy(mpe_plan p) {
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->gst) (void)hipStreamDestroy(p->gst);
   void* bufs[] = {p->W, p->tailbuf, p->phi, p->hphi, p->V64, p->Vf, p->fac, p->kin, p->hk, p->roots,
-                  p->partials, p->mats, p->rot, p->res, p->ticks};
+                  p->partials, p->mats, p->rot, p->res, p->ticks, p->fac2, p->kin2, p->rtmp};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (p->host_res) (void)hipHostFree(p->host_res);
@@ -752,7 +873,9 @@ mpe_status mpe_plan_create(mpe_plan* out, const int32_t grid[3], const double bo
   if (m > N) return MPE_ERR_INVALID_ARGUMENT;
   if (m > MAXM) return MPE_ERR_UNSUPPORTED;
   if (!size_ok(grid[0]) || !size_ok(grid[1]) || !size_ok(grid[2])) return MPE_ERR_UNSUPPORTED;
-  if (!plane_supported(prec == MPE_FP64, grid[0], grid[1]) || !pencil_supported(grid[2])) return MPE_ERR_UNSUPPORTED;
+  const bool planes_fit = plane_supported(prec == MPE_FP64, grid[0], grid[1]);
+  if (!pencil_supported(grid[2]) || (!planes_fit && (!row_supported(grid[0]) || !pencil_supported(grid[1]))))
+    return MPE_ERR_UNSUPPORTED;
 
   mpe_plan p = new mpe_plan_s();
   p->nx = grid[0];
@@ -820,7 +943,8 @@ mpe_status mpe_plan_create(mpe_plan* out, const int32_t grid[3], const double bo
             alloc((void**)&p->mats, 5 * (size_t)p->mp * p->mp * sizeof(double)) &&
             alloc((void**)&p->rot, p->rot_count * 4 * sizeof(double)) && alloc((void**)&p->res, p->res_bytes) &&
             alloc((void**)&p->ticks, 8 * sizeof(long long));
-  p->split_tail = tail_split(p->dbl, p->nx);
+  p->three_pass = !planes_fit;
+  p->split_tail = p->three_pass || tail_split(p->dbl, p->nx);
   if (ok && p->split_tail) ok = alloc(&p->tailbuf, (size_t)p->K * m * N * f);
   if (!ok) {
     mpe_plan_destroy(p);
@@ -982,6 +1106,12 @@ mpe_status mpe_residuals(mpe_plan p, const void* psi, const double* eig, double*
   return MPE_OK;
 }
 
+mpe_status mpe_forget_cached_h(mpe_plan p) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  p->rr_cache_psi = nullptr;
+  return MPE_OK;
+}
+
 mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh, double* re, double* re_perp) {
   if (!p) return MPE_ERR_INVALID_ARGUMENT;
   if (!psi) return fail(p, MPE_ERR_INVALID_ARGUMENT, "psi is null");
@@ -1036,6 +1166,56 @@ mpe_status mpe_set_graph(mpe_plan p, int32_t on) {
   return MPE_OK;
 }
 
+mpe_status mpe_set_propagator(mpe_plan p, int32_t kind) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (kind != MPE_PROP_EXPANSION && kind != MPE_PROP_ROMBERG6)
+    return fail(p, MPE_ERR_INVALID_ARGUMENT, "kind must be MPE_PROP_EXPANSION or MPE_PROP_ROMBERG6");
+  if (kind == MPE_PROP_ROMBERG6 && p->K != 2)
+    return fail(p, MPE_ERR_UNSUPPORTED, "the Romberg T6 is built from T4: it needs a plan of order 4");
+  if (kind == MPE_PROP_ROMBERG6 && !p->rtmp) {
+    const size_t tablen = (size_t)(p->nxh + p->ny + p->nz);
+    hipError_t e = hipMalloc(&p->fac2, (size_t)2 * p->K * p->N * p->fsz);
+    if (e == hipSuccess) e = hipMalloc(&p->kin2, (size_t)p->K * tablen * p->fsz);
+    if (e == hipSuccess) e = hipMalloc(&p->rtmp, (size_t)2 * p->m * p->N * p->fsz);
+    if (e != hipSuccess) {
+      for (void** b : {&p->fac2, &p->kin2, &p->rtmp})
+        if (*b) (void)hipFree(*b), *b = nullptr;
+      return fail(p, MPE_ERR_OUT_OF_MEMORY, "Romberg tables and staging blocks");
+    }
+    p->ws_bytes += (int64_t)((size_t)2 * p->K * p->N * p->fsz + (size_t)p->K * tablen * p->fsz +
+                             (size_t)2 * p->m * p->N * p->fsz);
+  }
+  p->prop = kind;
+  p->tab_dt = -1.0;   // rebuild the tables (the dt/2 set)
+  p->shape_ver++;     // re-capture the iteration graph
+  p->rr_cache_psi = nullptr;
+  return MPE_OK;
+}
+
+int32_t mpe_get_propagator(mpe_plan p) { return p ? p->prop : -1; }
+
+mpe_status mpe_set_three_pass(mpe_plan p, int32_t on) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (!on && !plane_supported(p->dbl, p->nx, p->ny))
+    return fail(p, MPE_ERR_UNSUPPORTED, "the plane pass does not hold this grid's planes");
+  if (on && !(row_supported(p->nx) && pencil_supported(p->ny)))
+    return fail(p, MPE_ERR_UNSUPPORTED, "no row or column pass for this grid");
+  if (on && !p->tailbuf) {
+    const size_t bytes = (size_t)p->K * p->m * p->N * p->fsz;
+    if (hipMalloc(&p->tailbuf, bytes) != hipSuccess) {
+      p->tailbuf = nullptr;
+      return fail(p, MPE_ERR_OUT_OF_MEMORY, "chain output buffers of the three-pass plan");
+    }
+    p->ws_bytes += (int64_t)bytes;
+  }
+  p->three_pass = on != 0;
+  p->split_tail = p->three_pass || tail_split(p->dbl, p->nx);
+  p->shape_ver++;
+  return MPE_OK;
+}
+
+int32_t mpe_get_three_pass(mpe_plan p) { return p ? (p->three_pass ? 1 : 0) : -1; }
+
 mpe_status mpe_set_variances(mpe_plan p, int32_t on) {
   if (!p) return MPE_ERR_INVALID_ARGUMENT;
   p->variances = on != 0;
@@ -1062,11 +1242,11 @@ mpe_status mpe_set_plane_shape(mpe_plan p, int32_t kernel_class, int32_t mode, i
   if (!p) return MPE_ERR_INVALID_ARGUMENT;
   const int c = kernel_class == MPE_KC_PLANE_FWD ? 0 : kernel_class == MPE_KC_PLANE_LINK ? 1 : -1;
   if (c < 0) return fail(p, MPE_ERR_INVALID_ARGUMENT, "kernel_class must be MPE_KC_PLANE_FWD or MPE_KC_PLANE_LINK");
-  if (mode < 0 || mode > 2) return fail(p, MPE_ERR_INVALID_ARGUMENT, "mode must be 0, 1 or 2");
-  if (mode > 0 && (blocks_per_cu < 1 || blocks_per_cu > 16))
+  if (mode < 0 || mode > 5) return fail(p, MPE_ERR_INVALID_ARGUMENT, "mode must lie in 0..5");
+  if (mode % 3 > 0 && (blocks_per_cu < 1 || blocks_per_cu > 16))
     return fail(p, MPE_ERR_INVALID_ARGUMENT, "blocks_per_cu must be in [1, 16] for a persistent shape");
   p->pmode[c] = mode;
-  p->pbpc[c] = mode > 0 ? blocks_per_cu : 0;
+  p->pbpc[c] = mode % 3 > 0 ? blocks_per_cu : 0;
   p->shape_ver++;
   return MPE_OK;
 }
@@ -1140,7 +1320,7 @@ mpe_status mpe_autotune(mpe_plan p, const void* psi, double dt, int32_t reps, co
   mpe_status s = ensure_tables(p, dt);
   if (s != MPE_OK) return s;
   // candidate shapes (mode, work-groups per CU), timed on steps psi -> phi
-  const int cand[][2] = {{0, 0}, {1, 1}, {2, 1}, {2, 2}, {2, 4}};
+  const int cand[][2] = {{0, 0}, {1, 1}, {2, 1}, {2, 2}, {2, 4}, {3, 0}, {4, 1}, {5, 1}, {5, 2}, {5, 4}};
   const int nc = (int)(sizeof cand / sizeof cand[0]);
   double best_ms[2] = {1e300, 1e300};
   int best_c[2] = {0, 0};
@@ -1455,6 +1635,10 @@ mpe_status mpe_batch_create(mpe_batch* out, int32_t count, const mpe_system_desc
       return s;
     }
     b->plans.push_back(p);
+    if (p->three_pass) {   // batched launches are plane passes
+      mpe_batch_destroy(b);
+      return MPE_ERR_UNSUPPORTED;
+    }
     s = mpe_set_potential(p, sd.V, hbar2_over_m);
     if (s != MPE_OK) {
       mpe_batch_destroy(b);

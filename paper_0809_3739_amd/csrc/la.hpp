@@ -57,6 +57,27 @@ struct RotateArgs {
   int m, mp;
 };
 
+// Point chunks of the overlap kernels: at most max_chunks chunks of >= 4096
+// points (multiples of 16), one work-group each; returns the count, *chunk
+// the chunk length.
+inline int gram_chunking(long N, long max_chunks, long* chunk) {
+  long nch = N / 4096 + (N % 4096 != 0);
+  nch = nch < 1 ? 1 : (nch > max_chunks ? max_chunks : nch);
+  long c = (N + nch - 1) / nch;
+  c = (c + 15) / 16 * 16;
+  *chunk = c;
+  return (int)((N + c - 1) / c);
+}
+// Point chunks of the rotation: at most 1024 chunks of >= 256 points (multiples of 64).
+inline int rot_chunking(long N, long* chunk) {
+  long nch = N / 256 + (N % 256 != 0);
+  nch = nch < 1 ? 1 : (nch > 1024 ? 1024 : nch);
+  long c = (N + nch - 1) / nch;
+  c = (c + 63) / 64 * 64;
+  *chunk = c;
+  return (int)((N + c - 1) / c);
+}
+
 hipError_t launch_gram(int is_double, const GramArgs& g, int nprod, int nchunks, hipStream_t st);
 // float32 states only: float32 MFMA, float64 slab sums and partials
 hipError_t launch_gram32(const GramArgs& g, int nprod, int nchunks, hipStream_t st);

@@ -302,11 +302,21 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
     auto locate = [&](long q, int& zq, Ptrs& Pq) {
       long sq;
       if constexpr (PERSIST != 0) {
-        zq = (int)(q % a.nz);
-        sq = q / a.nz + a.state0;
+        if (a.states_fast) {
+          sq = q % a.nstates + a.state0;
+          zq = (int)(q / a.nstates);
+        } else {
+          zq = (int)(q % a.nz);
+          sq = q / a.nz + a.state0;
+        }
       } else {
-        zq = blockIdx.x;
-        sq = (long)blockIdx.y + a.state0;
+        if (a.states_fast) {
+          zq = blockIdx.y;
+          sq = (long)blockIdx.x + a.state0;
+        } else {
+          zq = blockIdx.x;
+          sq = (long)blockIdx.y + a.state0;
+        }
       }
       Pq = ptrs_of(sq);
     };
@@ -559,7 +569,7 @@ __global__ __launch_bounds__(256) void pencil_kernel(PencilArgs a) {
   const F* ty = tab + a.NXH;
   for (int i = tid; i < NZ; i += 256) {
     rz_s[i] = reinterpret_cast<const cx<F>*>(a.rz)[i];
-    tz_s[i] = tab[a.NXH + a.NY + i];
+    if constexpr (KIND == PK_EXP || KIND == PK_ADD) tz_s[i] = tab[a.NXH + a.NY + i];
   }
   const cx<F>* rz = rz_s;
   const F* tz = tz_s;
@@ -571,24 +581,232 @@ __global__ __launch_bounds__(256) void pencil_kernel(PencilArgs a) {
   }
   __syncthreads();   // staged tables visible
   auto buf = [&](int i) { return &lds[i * CP + col]; };
-  fft<NZ, -1>(v, t, act, buf, rz);
-  if (act) {
-    const int ky = gc / a.NXH, kx = gc - ky * a.NXH;
-    if constexpr (KIND == PK_EXP) {
-      const F g = ty[ky] * tx[kx];
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = scale(v[m], tz[t + T * m] * g);
-    } else {
-      const F g = ty[ky] + tx[kx];
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = scale(v[m], tz[t + T * m] + g);
-    }
+  if constexpr (KIND == PK_FFT_INV) {
+    fft<NZ, +1>(v, t, act, buf, rz);
+  } else {
+    fft<NZ, -1>(v, t, act, buf, rz);
   }
-  fft<NZ, +1>(v, t, act, buf, rz);
+  if constexpr (KIND == PK_EXP || KIND == PK_ADD) {
+    if (act) {
+      const int ky = gc / a.NXH, kx = gc - ky * a.NXH;
+      if constexpr (KIND == PK_EXP) {
+        const F g = ty[ky] * tx[kx];
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = scale(v[m], tz[t + T * m] * g);
+      } else {
+        const F g = ty[ky] + tx[kx];
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = scale(v[m], tz[t + T * m] + g);
+      }
+    }
+    fft<NZ, +1>(v, t, act, buf, rz);
+  }
   if (act) {
 #pragma unroll
     for (int m = 0; m < E; ++m) data[(long)(t + T * m) * a.M + gcol] = v[m];
   }
+}
+
+
+// ------------------------------------------------------------------ row pass (three-pass plans)
+// The x transforms alone, for grids whose planes do not fit the plane pass
+// (nx != ny, or float64 planes above the LDS size): a row of NX real points and
+// its half spectrum X[0..NX/2] go through the NX/2-point complex FFT of the
+// packed row z_j = x_2j + i x_2j+1 and the split (W = exp(-2 pi i / NX),
+// Z[NX/2] = Z[0])
+//   X[k] = (Z[k] + conj Z[NX/2-k])/2 - i W^k (Z[k] - conj Z[NX/2-k])/2,
+// and back (unnormalised, as the plane pass: 2 Z[k] = (X[k] + conj X[NX/2-k])
+//   + i conj(W^k) (X[k] - conj X[NX/2-k])).
+// A row is carried by the TX lanes of its transform (consecutive lanes of one
+// wavefront); ROWS rows per work-group, each with its own LDS row for the
+// transform's exchanges and the split's mirrored reads.
+template <int NX>
+struct RowShape {
+  static constexpr int LX = NX / 2;
+  static constexpr int TX = Plan<LX>::T;
+  static constexpr int ROWS = 64 / TX < 16 ? 16 : 64 / TX;   // >= one wavefront of lanes
+  static constexpr int BLOCK = ROWS * TX;
+};
+
+template <typename F, int NX, int MODE>
+__global__ __launch_bounds__(RowShape<NX>::BLOCK) void row_kernel(PlaneArgs a) {
+  constexpr int LX = NX / 2, NXH = LX + 1, HALF = LX / 2;
+  using PX = Plan<LX>;
+  constexpr int TX = PX::T, EX = PX::E, ROWS = RowShape<NX>::ROWS;
+  constexpr int RS = LX + (LX - 1) / EX + 2;   // LDS row: padded exchange slots, or LX + 1 spectrum entries
+  static_assert(RS >= NXH, "a row holds the half spectrum");
+  __shared__ cx<F> lds[ROWS * RS];
+  __shared__ cx<F> tw_x[LX], tw_w[HALF + 1];
+  const int tid = threadIdx.x;
+  {
+    const cx<F>* gx = reinterpret_cast<const cx<F>*>(a.rx);
+    const cx<F>* gw = reinterpret_cast<const cx<F>*>(a.wpost);
+    for (int i = tid; i < LX; i += RowShape<NX>::BLOCK) tw_x[i] = gx[i];
+    for (int i = tid; i <= HALF; i += RowShape<NX>::BLOCK) tw_w[i] = gw[i];
+  }
+  __syncthreads();
+  const int tx = tid % TX, rl = tid / TX;
+  const long rows_per_state = (long)a.nz * a.ny;
+  const long row = (long)blockIdx.x * ROWS + rl;
+  const bool act = row < (long)a.nstates * rows_per_state;
+  const long rowc = act ? row : 0;
+  const long s = rowc / rows_per_state + a.state0;
+  const long zy = rowc % rows_per_state;          // z * ny + y
+  cx<F>* R = lds + rl * RS;
+  auto xbuf = [&](int i) { return R + i + i / EX; };
+  auto wk = [&](int k) -> cx<F> {
+    return k <= HALF ? tw_w[k] : cx<F>{-tw_w[LX - k].x, tw_w[LX - k].y};
+  };
+  gp<cx<F>> spec = (gp<cx<F>>)reinterpret_cast<cx<F>*>(a.spec) + s * a.spec_state_stride + zy * NXH;
+  gp<const F> fac = (a.fac && a.fac_index >= 0)
+                        ? (gp<const F>)reinterpret_cast<const F*>(a.fac) + (long)a.fac_index * a.fac_table_stride +
+                              zy * NX
+                        : nullptr;
+  cx<F> v[EX];
+
+  // half spectrum row -> 2 Z (strided order) through the LDS row
+  auto inverse_split = [&]() {
+#pragma unroll
+    for (int m = 0; m < EX; ++m) {
+      const int k = tx + TX * m;
+      if (act) R[k] = gload<F>(spec + k);
+    }
+    if (act && tx == 0) R[LX] = gload<F>(spec + LX);
+    wave_sync();
+#pragma unroll
+    for (int m = 0; m < EX; ++m) {
+      const int k = tx + TX * m;
+      const cx<F> X = R[k], Xm = conj(R[LX - k]);
+      v[m] = (X + Xm) + muli<+1>(cmulc(X - Xm, wk(k)));
+    }
+    wave_sync();
+  };
+  // Z (strided order) -> half spectrum row through the LDS row
+  auto forward_split_store = [&]() {
+    wave_sync();
+#pragma unroll
+    for (int m = 0; m < EX; ++m) R[tx + TX * m] = v[m];
+    if (tx == 0) R[LX] = v[0];
+    wave_sync();
+    if (act) {
+#pragma unroll
+      for (int m = 0; m < EX; ++m) {
+        const int k = tx + TX * m;
+        const cx<F> A = R[k], B = conj(R[LX - k]);
+        const cx<F> E = scale(A + B, F(0.5)), O = muli<-1>(scale(A - B, F(0.5)));
+        gstore<F>(spec + k, E + cmul(O, wk(k)));
+      }
+      if (tx == 0) {
+        const cx<F> A = R[LX], B = conj(R[0]);
+        const cx<F> E = scale(A + B, F(0.5)), O = muli<-1>(scale(A - B, F(0.5)));
+        gstore<F>(spec + LX, E + cmul(O, wk(LX)));
+      }
+    }
+  };
+
+  if constexpr (MODE == RW_FWD) {
+    gp<const cx<F>> src = reinterpret_cast<gp<const cx<F>>>((gp<const F>)reinterpret_cast<const F*>(a.real_in) +
+                                                          s * a.real_state_stride + zy * NX);
+    gp<const cx<F>> f2 = fac ? reinterpret_cast<gp<const cx<F>>>(fac) : nullptr;
+#pragma unroll
+    for (int m = 0; m < EX; ++m) {
+      v[m] = act ? gload<F>(src + tx + TX * m) : cx<F>{F(0), F(0)};
+      if (act && f2) {
+        const cx<F> fv = gload<F>(f2 + tx + TX * m);
+        v[m].x *= fv.x;
+        v[m].y *= fv.y;
+      }
+    }
+    fft<LX, -1, true>(v, tx, true, xbuf, tw_x);
+    forward_split_store();
+  } else {
+    inverse_split();
+    fft<LX, +1, true>(v, tx, true, xbuf, tw_x);
+    if constexpr (MODE == RW_LINK) {
+      gp<const cx<F>> f2 = reinterpret_cast<gp<const cx<F>>>(fac);
+#pragma unroll
+      for (int m = 0; m < EX; ++m) {
+        if (act) {
+          const cx<F> fv = gload<F>(f2 + tx + TX * m);
+          v[m].x *= fv.x;
+          v[m].y *= fv.y;
+        }
+      }
+      fft<LX, -1, true>(v, tx, true, xbuf, tw_x);
+      forward_split_store();
+    } else {
+      gp<cx<F>> dst = reinterpret_cast<gp<cx<F>>>((gp<F>)reinterpret_cast<F*>(a.real_out) +
+                                                s * a.real_state_stride + zy * NX);
+      if (act) {
+        if constexpr (MODE == RW_OUT) {
+          gp<const cx<F>> f2 = reinterpret_cast<gp<const cx<F>>>(fac);
+#pragma unroll
+          for (int m = 0; m < EX; ++m) {
+            const cx<F> fv = gload<F>(f2 + tx + TX * m);
+            gstore<F>(dst + tx + TX * m, cx<F>{v[m].x * fv.x, v[m].y * fv.y});
+          }
+        } else {   // RW_HTAIL: + V * phi
+          gp<const cx<F>> ph = reinterpret_cast<gp<const cx<F>>>((gp<const F>)reinterpret_cast<const F*>(a.real_in) +
+                                                               s * a.real_state_stride + zy * NX);
+          gp<const cx<F>> V2 = reinterpret_cast<gp<const cx<F>>>((gp<const F>)reinterpret_cast<const F*>(a.fac) +
+                                                               zy * NX);
+#pragma unroll
+          for (int m = 0; m < EX; ++m) {
+            const cx<F> pv = gload<F>(ph + tx + TX * m), wv = gload<F>(V2 + tx + TX * m);
+            gstore<F>(dst + tx + TX * m, cx<F>{v[m].x + wv.x * pv.x, v[m].y + wv.y * pv.y});
+          }
+        }
+      }
+    }
+  }
+}
+
+template <typename F, int N>
+static hipError_t launch_rows_n(int mode, const PlaneArgs& a0, int ny, int nz, int nstates, hipStream_t st) {
+  PlaneArgs a = a0;
+  a.ny = ny;
+  a.nz = nz;
+  a.nstates = nstates;
+  const long rows = (long)nstates * nz * ny;
+  constexpr int ROWS = RowShape<N>::ROWS;
+  const dim3 grid((unsigned)((rows + ROWS - 1) / ROWS)), block(RowShape<N>::BLOCK);
+  switch (mode) {
+    case RW_FWD: hipLaunchKernelGGL((row_kernel<F, N, RW_FWD>), grid, block, 0, st, a); break;
+    case RW_LINK: hipLaunchKernelGGL((row_kernel<F, N, RW_LINK>), grid, block, 0, st, a); break;
+    case RW_OUT: hipLaunchKernelGGL((row_kernel<F, N, RW_OUT>), grid, block, 0, st, a); break;
+    case RW_HTAIL: hipLaunchKernelGGL((row_kernel<F, N, RW_HTAIL>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename F>
+static hipError_t launch_rows_t(int mode, int nx, const PlaneArgs& a, int ny, int nz, int ns, hipStream_t st) {
+  switch (nx) {
+    case 8: return launch_rows_n<F, 8>(mode, a, ny, nz, ns, st);
+    case 16: return launch_rows_n<F, 16>(mode, a, ny, nz, ns, st);
+    case 32: return launch_rows_n<F, 32>(mode, a, ny, nz, ns, st);
+    case 48: return launch_rows_n<F, 48>(mode, a, ny, nz, ns, st);
+    case 64: return launch_rows_n<F, 64>(mode, a, ny, nz, ns, st);
+    case 96: return launch_rows_n<F, 96>(mode, a, ny, nz, ns, st);
+    case 128: return launch_rows_n<F, 128>(mode, a, ny, nz, ns, st);
+    case 192: return launch_rows_n<F, 192>(mode, a, ny, nz, ns, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool row_supported(int nx) {
+  switch (nx) {
+    case 8: case 16: case 32: case 48: case 64: case 96: case 128: case 192: return true;
+    default: return false;
+  }
+}
+
+hipError_t launch_rows(int is_double, int mode, int nx, const PlaneArgs& a, int ny, int nz, int nstates,
+                       hipStream_t st) {
+  if (nstates <= 0) return hipSuccess;
+  return is_double ? launch_rows_t<double>(mode, nx, a, ny, nz, nstates, st)
+                   : launch_rows_t<float>(mode, nx, a, ny, nz, nstates, st);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -612,14 +830,16 @@ static hipError_t launch_plane_n(int mode, const PlaneArgs& a, int nz, int nstat
       return hipGetLastError();
     }
   }
-  // z planes fastest (neighbouring work-groups stream neighbouring planes of one
-  // state), except in the tail pass: there states go fastest, so the work-groups
-  // in flight share a few z planes and the 2K potential-factor planes they read
-  // stay in every XCD's L2 while the states stream past
+  // The H and single-chain passes walk z planes fastest; the forward and link
+  // passes take the order of PlaneArgs::states_fast; the tail pass walks states
+  // fastest, so the work-groups in flight share a few z planes and the 2K
+  // potential-factor planes they read stay in every XCD's L2 while the states
+  // stream past
   dim3 grid(nz, nstates), grid_t(nstates, nz);
+  const dim3 grid_fl = a.states_fast ? grid_t : grid;   // forward / link: either order
   switch (mode) {
-    case PM_FWD: hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD, 0>), grid, block, 0, st, a); break;
-    case PM_LINK: hipLaunchKernelGGL((plane_kernel<F, N, PM_LINK, 0>), grid, block, 0, st, a); break;
+    case PM_FWD: hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD, 0>), grid_fl, block, 0, st, a); break;
+    case PM_LINK: hipLaunchKernelGGL((plane_kernel<F, N, PM_LINK, 0>), grid_fl, block, 0, st, a); break;
     case PM_TAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_TAIL, 0>), grid_t, block, 0, st, a); break;
     case PM_HTAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_HTAIL, 0>), grid, block, 0, st, a); break;
     case PM_OUT: hipLaunchKernelGGL((plane_kernel<F, N, PM_OUT, 0>), grid, block, 0, st, a); break;
@@ -632,10 +852,13 @@ template <typename F, int N>
 static hipError_t launch_pencil_n(int kind, const PencilArgs& a, int nstates, hipStream_t st) {
   constexpr int C = PencilCols<N>::value;
   dim3 grid((a.M + C - 1) / C, nstates);
-  if (kind == PK_EXP)
-    hipLaunchKernelGGL((pencil_kernel<F, N, PK_EXP>), grid, dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL((pencil_kernel<F, N, PK_ADD>), grid, dim3(256), 0, st, a);
+  switch (kind) {
+    case PK_EXP: hipLaunchKernelGGL((pencil_kernel<F, N, PK_EXP>), grid, dim3(256), 0, st, a); break;
+    case PK_ADD: hipLaunchKernelGGL((pencil_kernel<F, N, PK_ADD>), grid, dim3(256), 0, st, a); break;
+    case PK_FFT_FWD: hipLaunchKernelGGL((pencil_kernel<F, N, PK_FFT_FWD>), grid, dim3(256), 0, st, a); break;
+    case PK_FFT_INV: hipLaunchKernelGGL((pencil_kernel<F, N, PK_FFT_INV>), grid, dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -7,7 +7,10 @@ namespace mpe {
 constexpr int MAX_K = 6;  // order 2K <= 12
 
 enum PlaneMode { PM_FWD = 0, PM_LINK = 1, PM_TAIL = 2, PM_HTAIL = 3, PM_OUT = 4 };
-enum PencilKind { PK_EXP = 0, PK_ADD = 1 };
+enum PencilKind { PK_EXP = 0, PK_ADD = 1, PK_FFT_FWD = 2, PK_FFT_INV = 3 };
+// Row-pass modes of the three-pass plans (x transforms alone): as the plane
+// modes of the same names, without the y transform.
+enum RowMode { RW_FWD = 0, RW_LINK = 1, RW_OUT = 2, RW_HTAIL = 3 };
 
 // Per-state addresses for launches that cover states of several systems of
 // one grid (batched uneven systems).  One entry per state of the launch.
@@ -50,7 +53,13 @@ struct PlaneArgs {
   // work-group per CU (1) or of the one-plane launch (2)
   int persist_mode;
   int persist_blocks;
+  // PM_FWD / PM_LINK plane order: 0 = z planes fastest (neighbouring work-groups
+  // take neighbouring planes of one state), 1 = states fastest (the work-groups
+  // in flight share a few z planes, so each factor-table plane is fetched into
+  // an XCD's L2 once and read there by every state)
+  int states_fast;
   int nz, nstates;            // set by the launcher for persistent launches
+  int ny;                     // row passes: rows per z plane
 };
 
 struct PencilArgs {
@@ -76,6 +85,10 @@ bool tail_split(int is_double, int nx);
 hipError_t launch_combine(int is_double, const void* tmp, long stride, int K, const double* coef, void* dst, long n,
                           hipStream_t st);
 bool pencil_supported(int nz);
+bool row_supported(int nx);
+// Row pass over the rows of states [state0, state0 + nstates): nstates * nz * ny rows of nx points.
+hipError_t launch_rows(int is_double, int mode, int nx, const PlaneArgs& a, int ny, int nz, int nstates,
+                       hipStream_t st);
 hipError_t launch_plane(int is_double, int mode, int nx, const PlaneArgs& a, int nz, int nstates, hipStream_t st);
 hipError_t launch_pencil(int is_double, int kind, int nz, const PencilArgs& a, int nstates, hipStream_t st);
 

@@ -7,9 +7,12 @@ For each order 2K the C60-like cage is solved from the same random start with
 the step-size protocol of Section III (``solver.solve``: dt0, halving after
 the per-step variance test) to max_{j < n} R^H_j <= gamma, and the seconds,
 iterations, levels, final dt, state propagations and T2 applications per state
-are reported, one JSON line per order.
+are reported, one JSON line per order.  The order "r6" is the Romberg-type
+sixth-order operator of Eq. sixp built from the order-4 expansion
+(-T4(dt)/15 + 16 T4(dt/2)^2/15, nine T2 applications per state and step),
+which Section II contrasts with the expansion's six at order 6.
 
-    python -m paper_0809_3739_amd.order_study [--grid 64] [--orders 2,4,6,8,10,12]
+    python -m paper_0809_3739_amd.order_study [--grid 64] [--orders 2,4,6,8,10,12,r6]
         [--precision fp64] [--states 120] [--guards 5] [--gamma 1e-8] [--lock]
 """
 from __future__ import annotations
@@ -26,8 +29,10 @@ import workloads as W
 from . import solver
 
 
-def t2_per_step(order: int) -> int:
-    K = order // 2
+def t2_per_step(order) -> int:
+    if order == "r6":
+        return 9
+    K = int(order) // 2
     return K * (K + 1) // 2
 
 
@@ -38,8 +43,10 @@ def run(grid: int = 64, orders=(2, 4, 6, 8, 10, 12), precision: str = "fp64", n_
     m = n_states + n_guard
     rows = []
     for order in orders:
-        plan = solver.Plan(s.grid, s.box, n_states, order, precision, n_guard=n_guard)
+        plan = solver.Plan(s.grid, s.box, n_states, 4 if order == "r6" else int(order), precision, n_guard=n_guard)
         plan.set_potential(s.V)
+        if order == "r6":
+            plan.set_propagator("romberg6")
         psi = plan.new_states(W.random_states(seed, m, s.grid))
         last = [time.perf_counter()]
 
@@ -57,7 +64,8 @@ def run(grid: int = 64, orders=(2, 4, 6, 8, 10, 12), precision: str = "fp64", n_
         row = {"order": order, "grid": grid, "precision": precision, "states": m, "seconds": round(secs, 3),
                "iterations": r.iterations, "levels": r.levels, "final_dt": r.dt, "converged": bool(r.converged),
                "max_rh": float(np.max(r.rh[:n_states])), "state_propagations": r.propagations,
-               "t2_per_state": int(r.propagations * t2_per_step(order) / m), "lock": lock,
+               "t2_per_state": int(r.propagations * t2_per_step(order) / m), "t2_per_step": t2_per_step(order),
+               "lock": lock,
                "eig0": float(r.eig[0]), "eig_last": float(r.eig[n_states - 1])}
         log(json.dumps(row))
         rows.append(row)
@@ -79,7 +87,8 @@ def main(argv=None):
     ap.add_argument("--lock", action="store_true", help="selective propagation at gamma/10")
     ap.add_argument("--max-levels", type=int, default=12)
     a = ap.parse_args(argv)
-    run(a.grid, tuple(int(x) for x in a.orders.split(",")), a.precision, a.states, a.guards, a.gamma, a.dt0,
+    run(a.grid, tuple(x if x == "r6" else int(x) for x in a.orders.split(",")), a.precision, a.states, a.guards,
+        a.gamma, a.dt0,
         a.lock, max_levels=a.max_levels, log=lambda msg: print(msg, flush=True))
 
 

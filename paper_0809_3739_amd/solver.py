@@ -50,6 +50,7 @@ class Plan:
         _lib.check(code)
         self.h = h
         self.shape = (self.m, self.grid[2], self.grid[1], self.grid[0])
+        self._hkey = None   # (address, torch version) of the block whose H psi the library keeps
 
     # --------------------------------------------------------------- plumbing
     def close(self):
@@ -65,6 +66,16 @@ class Plan:
 
     def _check(self, code):
         _lib.check(code, self.h)
+
+    def _cached_h_valid_for(self, t: torch.Tensor):
+        """The library keeps H psi of the last Rayleigh-Ritz / iteration block keyed by its
+        address only; drop it unless ``t`` is that block, untouched by torch since."""
+        if self._hkey is not None and self._hkey != (t.data_ptr(), t._version):
+            self._check(self.lib.mpe_forget_cached_h(self.h))
+            self._hkey = None
+
+    def _remember_h(self, t: torch.Tensor):
+        self._hkey = (t.data_ptr(), t._version)
 
     def _arr(self, t: torch.Tensor, shape=None):
         shape = self.shape if shape is None else shape
@@ -94,33 +105,43 @@ class Plan:
         self._check(self.lib.mpe_set_potential(self.h, C.c_void_p(Vt.data_ptr()), float(hbar2_over_m)))
 
     def step(self, psi: torch.Tensor, dt: float):
+        self._hkey = None   # the library drops its H psi on every call but the three below
         self._check(self.lib.mpe_step(self.h, self._arr(psi), float(dt)))
 
     def apply_h(self, psi: torch.Tensor, hpsi: torch.Tensor | None = None) -> torch.Tensor:
         out = torch.empty_like(psi) if hpsi is None else hpsi
+        self._hkey = None
         self._check(self.lib.mpe_apply_h(self.h, self._arr(psi), self._arr(out)))
         return out
 
     def orthonormalize(self, psi: torch.Tensor):
+        self._hkey = None
         self._check(self.lib.mpe_orthonormalize(self.h, self._arr(psi)))
 
     def rayleigh_ritz(self, psi: torch.Tensor) -> np.ndarray:
         eig = np.zeros(self.m)
+        self._hkey = None
         self._check(self.lib.mpe_rayleigh_ritz(self.h, self._arr(psi), _dptr(eig)))
+        self._remember_h(psi)
         return eig
 
     def residuals(self, psi: torch.Tensor, eig, with_re: bool = False):
         eig = np.ascontiguousarray(eig, dtype=np.float64)
         rh = np.zeros(self.m)
         re = np.zeros(self.m) if with_re else None
+        self._cached_h_valid_for(psi)
         self._check(self.lib.mpe_residuals(self.h, self._arr(psi), _dptr(eig), _dptr(rh),
                                            _dptr(re) if with_re else None))
+        self._remember_h(psi)   # residuals leave the block and its H psi in place
         return (rh, re) if with_re else rh
 
     def iterate(self, psi: torch.Tensor, dt: float) -> dict:
         out = {k: np.zeros(self.m) for k in ("eig", "rh", "re", "re_perp")}
+        self._cached_h_valid_for(psi)
+        self._hkey = None
         self._check(self.lib.mpe_iterate(self.h, self._arr(psi), float(dt), _dptr(out["eig"]), _dptr(out["rh"]),
                                          _dptr(out["re"]), _dptr(out["re_perp"])))
+        self._remember_h(psi)
         return out
 
     def small_dense_phases(self) -> dict:
@@ -144,6 +165,24 @@ class Plan:
         """Form R^E / R^E_perp in the following iterations (default) or skip them
         (NaN outputs, one overlap product fewer); see mpe_set_variances."""
         self._check(self.lib.mpe_set_variances(self.h, 1 if on else 0))
+
+    def set_propagator(self, kind: str):
+        """"expansion" (the plan's order-2K multi-product expansion, default) or
+        "romberg6" (order-4 plans: -T4(dt)/15 + 16 T4(dt/2)^2/15, Eq. sixp)."""
+        self._hkey = None
+        self._check(self.lib.mpe_set_propagator(self.h, {"expansion": 0, "romberg6": 1}[kind]))
+
+    def set_three_pass(self, on: bool):
+        """Transforms as separate x, y and z passes (see mpe_set_three_pass)."""
+        self._check(self.lib.mpe_set_three_pass(self.h, 1 if on else 0))
+
+    @property
+    def three_pass(self) -> bool:
+        return bool(self.lib.mpe_get_three_pass(self.h) == 1)
+
+    @property
+    def propagator(self) -> str:
+        return ["expansion", "romberg6"][int(self.lib.mpe_get_propagator(self.h))]
 
     @property
     def locked(self) -> int:
@@ -288,7 +327,8 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
           n_check: int | None = None, margin: float = 0.01, max_iter_per_level: int = 2000,
           max_levels: int = 30, orthonormalize_first: bool = True, callback=None,
           stall_window: int | None = None, stall_gain: float = 0.02, accept=None,
-          lock_tol: float | None = None, variance_every: int = 1) -> SolveResult:
+          lock_tol: float | None = None, variance_every: int = 1, re_tol: float | None = None,
+          level_stall: int | None = None) -> SolveResult:
     """Iterate with the protocol of Section III until R^H_j < gamma for the
     first ``n_check`` states.
 
@@ -317,12 +357,26 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
     locks are dropped when dt changes, and a level only ends on an iteration
     without locks, so its R^E test sees every state propagated.
 
+    A level also ends when max R^H has not improved by the fraction
+    ``stall_gain`` over the last ``level_stall`` iterations (default 20 for
+    float32 plans, off for float64): in float32, R^E_perp carries a floor near
+    1e-7 of the propagated norm (the block is orthonormal to float32 rounding
+    only), above the variance bound, so the fixed point at this dt shows as R^H
+    no longer falling; the R^H test then decides as after a variance-test exit.
+    (With ``stall_window`` a stall ends the whole solve first.)
+
+    With ``re_tol`` the fixed-dt test is max_j R^E_perp_j exp(2 dt theta_j)
+    <= re_tol instead: R^E_perp relative to the propagated norm S_jj ~
+    exp(-2 dt theta_j), e.g. to converge every level to its fixed point.
+
     With ``variance_every`` = k > 1 the variances are formed only in every k-th
     iteration of a level (and in the iteration that confirms a level's end);
     the others skip the overlap M = Psi^T Phi (``Plan.set_variances``) and
     cannot end a level.
     """
     n_check = plan.n_states if n_check is None else n_check
+    if level_stall is None and getattr(plan, "precision", "fp64") == "fp32":
+        level_stall = 20
     t0 = time.perf_counter()
     if orthonormalize_first:
         plan.orthonormalize(psi)
@@ -342,7 +396,7 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
     plan.set_variances(True)
     try:
         for level in range(max_levels):
-            ge = margin * gamma * dt * dt
+            ge = margin * gamma * dt * dt if re_tol is None else re_tol
             rh_level = []
             plan.set_locked(0)
             var_next = True
@@ -355,6 +409,8 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
                 total += 1
                 props += plan.m - locked
                 rep = float(np.max(out["re_perp"][:n_check]))
+                if re_tol is not None:
+                    rep = float(np.max(out["re_perp"][:n_check] * np.exp(2.0 * dt * out["eig"][:n_check])))
                 rhm = float(np.max(out["rh"][:n_check]))
                 rh_level.append(rhm)
                 hist.append({"dt": dt, "it": total, "re_perp": rep, "rh": rhm, "eig0": float(out["eig"][0]),
@@ -373,6 +429,9 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
                     before = min(rh_level[:-stall_window])
                     if min(rh_level[-stall_window:]) > (1.0 - stall_gain) * before:
                         return result(out["eig"], out["rh"], level + 1, False, stalled=True)
+                if level_stall and it >= level_stall and locked == 0:
+                    if min(rh_level[-level_stall:]) > (1.0 - stall_gain) * min(rh_level[:-level_stall]):
+                        break
                 confirm = False
                 if lock_tol is not None:
                     nl = 0

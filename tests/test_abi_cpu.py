@@ -88,8 +88,10 @@ def test_plan_create_argument_validation(lib):
     assert lib.mpe_plan_create(C.byref(h), g, b, 0, 4, 0, 0, None) == 1            # no states
     bad = (C.c_double * 3)(16.0, -1.0, 16.0)
     assert lib.mpe_plan_create(C.byref(h), g, bad, 4, 4, 0, 0, None) == 1          # box
-    g192 = (C.c_int32 * 3)(192, 192, 192)
-    assert lib.mpe_plan_create(C.byref(h), g192, b, 4, 4, 0, 0, None) == 2         # fp64 at 192: no kernel
+    g384 = (C.c_int32 * 3)(384, 192, 192)
+    assert lib.mpe_plan_create(C.byref(h), g384, b, 4, 4, 0, 0, None) == 2         # no 384-point row pass
+    g36 = (C.c_int32 * 3)(32, 36, 32)
+    assert lib.mpe_plan_create(C.byref(h), g36, b, 4, 4, 1, 0, None) == 2          # no 36-point column pass
     assert lib.mpe_plan_create(None, g, b, 4, 4, 0, 0, None) == 1
 
 

@@ -121,3 +121,74 @@ def test_variances_every_k_iterations_and_for_the_confirming_one():
     assert plan.locked_seen == [0, 0, 1, 1, 0, 0]
     assert plan.dts == [0.4] * 5 + [0.2]
     assert plan._var is True        # restored at the end
+
+
+# ------------------------------------------------------------------ the Plan wrapper's cached H psi
+class _RecordingLib:
+    """Stands in for libmpe: records the entry points called, returns MPE_OK."""
+
+    def __init__(self):
+        self.calls = []
+
+    def __getattr__(self, name):
+        def call(*args):
+            self.calls.append(name)
+            return 0
+        return call
+
+
+def _plan_on_recording_lib():
+    import ctypes as C
+    import torch
+    p = object.__new__(solver.Plan)
+    p.lib = _RecordingLib()
+    p.h = None
+    p.m = p.n_states = 2
+    p.dtype = torch.float32
+    p.shape = (2, 2, 2, 2)
+    p._hkey = None
+    p._arr = lambda t, shape=None: C.c_void_p(t.data_ptr())
+    return p
+
+
+def test_plan_drops_the_cached_h_psi_when_the_block_changes_outside_the_library():
+    """The library keys its kept H psi by the block's address only; the wrapper
+    asks it to forget H psi when torch has written the block (its version
+    counter moved) or another block comes in, and not otherwise."""
+    import torch
+    p = _plan_on_recording_lib()
+    forgets = lambda: p.lib.calls.count("mpe_forget_cached_h")   # noqa: E731
+    x = torch.zeros(p.shape)
+    p.iterate(x, 0.1)                     # the library now keeps H x
+    p.residuals(x, np.zeros(2))
+    p.iterate(x, 0.1)
+    assert forgets() == 0
+    x.mul_(2.0)                           # torch writes the block in place
+    p.residuals(x, np.zeros(2))
+    assert forgets() == 1
+    y = torch.zeros(p.shape)              # a different block
+    p.iterate(y, 0.1)
+    assert forgets() == 2
+    p.rayleigh_ritz(y)
+    p.residuals(y, np.zeros(2))
+    assert forgets() == 2
+    p.step(y, 0.1)                        # the library drops its H psi itself on other calls
+    y.add_(1.0)
+    p.iterate(y, 0.1)
+    assert forgets() == 2
+
+
+def test_float32_level_ends_when_rh_stops_falling():
+    """Float32 plans: R^E_perp sits on its float32 floor (never below the variance
+    bound), so a level ends when max R^H stops improving; the R^H test then halves dt."""
+    m = 2
+    plateau = [([1e-6, 1e-6], [1e-7, 1e-7])] * 25
+    script = plateau + [([1e-20] * m, [1e-7] * m)]
+    plan = ScriptedPlan(m, 2, script)
+    plan.precision = "fp32"
+    r = solver.solve(plan, None, dt0=0.4, gamma=1e-10)
+    assert r.converged
+    assert plan.dts == [0.4] * 21 + [0.2] * 5      # 20-iteration stall window, then halving
+    plan64 = ScriptedPlan(m, 2, [([1e-6, 1e-6], [1e-7, 1e-7])] * 30 + [([1e-20] * m, [1e-7] * m)])
+    r64 = solver.solve(plan64, None, dt0=0.4, gamma=1e-10, max_iter_per_level=30)
+    assert plan64.dts == [0.4] * 30 + [0.2]       # float64: no stall exit, the level runs to its cap

@@ -130,6 +130,30 @@ def random_states(seed: int, count: int, grid) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal((count, nz, ny, nx))
 
 
+def disjoint_sign_states(seed: int, count: int, grid) -> np.ndarray:
+    """``count`` states, exactly orthonormal and exactly representable in float32.
+
+    The grid points are shuffled (seeded) and dealt out in disjoint sets of 4^k
+    points, 4^k the largest power of four with count * 4^k <= N; state j is
+    +-2^-k (random signs) on its set and 0 elsewhere, so every inner product is
+    exactly 0 or 1 in any precision.  float64 [count][nz][ny][nx].
+    """
+    nx, ny, nz = (int(g) for g in grid)
+    N = nx * ny * nz
+    k = 0
+    while count * 4 ** (k + 1) <= N:
+        k += 1
+    if count * 4 ** k > N:
+        raise ValueError("more states than grid points")
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(N)
+    signs = rng.integers(0, 2, (count, 4 ** k)) * 2.0 - 1.0
+    out = np.zeros((count, N), dtype=np.float64)
+    for j in range(count):
+        out[j, perm[j * 4 ** k:(j + 1) * 4 ** k]] = signs[j] * 2.0 ** (-k)
+    return out.reshape(count, nz, ny, nx)
+
+
 def plane_wave_states(count: int, grid, box) -> np.ndarray:
     """The ``count`` lowest real plane waves of the periodic box, float64 [count][nz][ny][nx].
 
