@@ -282,6 +282,43 @@ mpe_status mpe_profile_enable(mpe_plan p, int32_t on);
 mpe_status mpe_get_kernel_times(mpe_plan p, double* ms, int64_t* launches);
 
 /* ---------------------------------------------------------------------------
+ * Allocation-free orthonormalisation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the work of mpe_orthonormalize without a plan.
+ *
+ * psi: device array [m][n_points] of double (MPE_FP64) or float (MPE_FP32),
+ * orthonormalised in place (S = Psi Psi^T on float64 MFMA, S = L L^T,
+ * Psi <- L^-1 Psi) on hip_stream (NULL = null stream); the call synchronises
+ * that stream to read the status.  Limits: 1 <= m <= 128 and m <= n_points,
+ * else MPE_ERR_UNSUPPORTED (m > 128) or MPE_ERR_INVALID_ARGUMENT, with a
+ * message in mpe_noalloc_last_error().
+ *
+ * Every intermediate (overlap partials of up to 64 point chunks, S, L^-T,
+ * status) lives in one file-scope device array of MPE_NOALLOC_SCRATCH_BYTES
+ * bytes that each GPU the library runs on holds until the process ends; no
+ * call allocates or frees memory.  All calls on one GPU share that array, so
+ * calls that overlap in time on one GPU (two host threads, or two streams
+ * without ordering) race and must not be issued.  Up to 64 * 4096 points the
+ * overlap is chunked exactly as in a plan and the result equals
+ * mpe_orthonormalize bitwise; beyond, the sums are grouped into 64 chunks
+ * instead of up to 256 (float64 rounding differences only).
+ * On NOT_POSITIVE_DEFINITE or NONFINITE psi is left unchanged.
+ *
+ * Set-up: the array's device address is resolved once per GPU, by
+ * mpe_noalloc_prepare() or else by the first call on that GPU; the HIP runtime
+ * may materialise the array's storage at that moment (once per GPU, for the
+ * life of the process).  Callers that must not allocate at all call
+ * mpe_noalloc_prepare() with each GPU current beforehand. */
+#define MPE_NOALLOC_SCRATCH_BYTES 8656912
+mpe_status mpe_orthonormalize_noalloc(void* psi, int32_t m, int64_t n_points, mpe_precision prec, void* hip_stream);
+/* Resolve the scratch array on the current GPU (see above).  MPE_ERR_DEVICE on a
+ * HIP failure, with a message in mpe_noalloc_last_error(). */
+mpe_status mpe_noalloc_prepare(void);
+/* Message of the calling thread's last failed mpe_orthonormalize_noalloc or
+ * mpe_noalloc_prepare ("" after success). */
+const char* mpe_noalloc_last_error(void);
+
+/* ---------------------------------------------------------------------------
  * Batched uneven systems: many independent eigenproblems (different grids,
  * state counts and potentials, one order and precision) advanced together.
  * Systems with the same grid share every propagation and H launch (one launch

@@ -66,6 +66,9 @@ SIGNATURES = {
     "mpe_small_dense_phases": (C.c_int, [_vp, _dp]),
     "mpe_profile_enable": (C.c_int, [_vp, _i32]),
     "mpe_get_kernel_times": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64)]),
+    "mpe_orthonormalize_noalloc": (C.c_int, [_vp, _i32, C.c_int64, C.c_int, _vp]),
+    "mpe_noalloc_last_error": (C.c_char_p, []),
+    "mpe_noalloc_prepare": (C.c_int, []),
     "mpe_batch_create": (C.c_int, [C.POINTER(_vp), _i32, C.POINTER(SystemDesc), _i32, C.c_int, C.c_double, _vp]),
     "mpe_batch_destroy": (C.c_int, [_vp]),
     "mpe_batch_last_error": (C.c_char_p, [_vp]),
