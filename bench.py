@@ -7,7 +7,8 @@ Workload: the C60-like Gaussian-well cage (60 wells on a truncated
 icosahedron of radius 6.7 bohr, V0 = 1.2 Ha, sigma = 0.9 bohr) in a 32-bohr
 periodic box on a 128^3 grid, 120 states + 5 guard states, multi-product
 order 12 (21 T2 applications per state per step), float32 transforms with the
-float64 c_k combination, overlaps, Cholesky and Rayleigh-Ritz.  A step is one
+float64 c_k combination, Cholesky and Rayleigh-Ritz, overlap GEMMs on float32 MFMA
+(float32 accumulation over 32-point slabs, float64 across them).  A step is one
 fused iteration: propagate all states, apply H, overlaps, Cholesky +
 Rayleigh-Ritz, rotation with the R^H epilogue, readback of 4 x 125 doubles.
 States start i.i.d. N(0,1) (seeded) and are resident in HBM before timing.
@@ -130,6 +131,15 @@ def bench_batch(args, P, W, torch):
         batch.iterate(psis, dt)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / args.steps
+    # propagation alone: the batched in-place step (every system's T_order(dt) psi, the
+    # same propagation launches as inside the iteration, launched eagerly)
+    batch.step(psis, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.step(psis, dt)
+    torch.cuda.synchronize()
+    t_prop = (time.perf_counter() - t0) / args.steps
     # the same systems as separate plans, one after another
     plans = []
     for i, sy in enumerate(systems):
@@ -165,6 +175,9 @@ def bench_batch(args, P, W, torch):
         "speedup_vs_separate_plans": round(t_sep / t_batch, 3),
         "launches_per_step": batch.launches_per_step,
         "propagate_algorithmic_GB_per_step": round(bytes_it / 1e9, 3),
+        "propagate_ms_per_step": round(t_prop * 1e3, 3),
+        "propagate_GB_per_s": round(bytes_it / t_prop / 1e9, 1),
+        "propagate_frac_of_hbm_peak": round(bytes_it / t_prop / 1e9 / HBM_PEAK_GBS, 4),
     }))
 
 
@@ -179,8 +192,9 @@ def main():
     ap.add_argument("--dt", type=float, default=0.5)
     ap.add_argument("--states-per-launch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--gemm", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"],
-                    help="overlap GEMMs on float64 MFMA (default) or float32 MFMA (float32 plans)")
+    ap.add_argument("--gemm", default=None, choices=["fp64", "fp32", "bf16x3", "bf16x6"],
+                    help="overlap GEMMs: float32 MFMA for float32 plans (default, the precision split), "
+                         "float64 MFMA for float64 plans, or a BF16 split")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default plane-pass shapes instead of timing the candidates first")
     ap.add_argument("--no-solve", action="store_true",
@@ -211,6 +225,8 @@ def main():
     s = W.c60_system(args.grid, 32.0, n_states)
     plan = P.Plan(s.grid, s.box, n_states, args.order, args.precision, n_guard=n_guard)
     plan.set_potential(s.V)
+    if args.gemm is None:
+        args.gemm = "fp32" if args.precision == "fp32" else "fp64"
     if args.gemm != "fp64":
         plan.set_gemm_precision(args.gemm)
     if args.states_per_launch:

@@ -254,18 +254,29 @@ mpe_status mpe_set_plane_shape(mpe_plan p, int32_t kernel_class, int32_t mode, i
 enum { MPE_GEMM_FP64 = 0, MPE_GEMM_FP32 = 1, MPE_GEMM_BF16X3 = 2, MPE_GEMM_BF16X6 = 3 };
 mpe_status mpe_set_gemm_precision(mpe_plan p, int32_t mode);
 
+/* Work-group shape of the pencil (z) passes: tile 0 = 256 threads (default),
+ * 1 = 128 threads, 2 = 512 threads, the columns per work-group scaling alike
+ * (shapes a grid cannot take, such as 512 threads where the exchange rows would
+ * not fit 64 KB of LDS, run as tile 0).  Results are bitwise identical for
+ * every shape.  MPE_ERR_INVALID_ARGUMENT outside 0..2. */
+mpe_status mpe_set_pencil_shape(mpe_plan p, int32_t tile);
+/* Current pencil tile (-1 for a null plan). */
+int32_t mpe_get_pencil_shape(mpe_plan p);
+
 /* Current shapes: shape[4] = {fwd mode, fwd blocks_per_cu, link mode, link blocks_per_cu}. */
 mpe_status mpe_get_plane_shape(mpe_plan p, int32_t* shape);
 
 /* Autotuner: times the candidate plane shapes (mode, blocks per CU) in
  * {(0,0), (1,1), (2,1), (2,2), (2,4)} and the same five with states fastest
- * (modes 3..5) on `reps` steps of psi (read only; the
- * steps write the plan's workspace) at dt, and keeps the fastest shape per
- * pass.  With cache_path (may be NULL), a line "key|fwd_mode fwd_bpc
- * link_mode link_bpc" keyed by device, CU count, grid, precision, block size
- * and order is looked up first (no timing on a hit) and appended after
- * tuning.  ms_out (may be NULL) receives the chosen shapes' milliseconds per
- * step for the forward and link passes (-1 on a cache hit).  Synchronises. */
+ * (modes 3..5), then the pencil tiles 0..2 with the chosen plane shapes, on
+ * `reps` steps of psi (read only; the steps write the plan's workspace) at dt,
+ * and keeps the fastest shape per pass.  With cache_path (may be NULL), a line
+ * "key|fwd_mode fwd_bpc link_mode link_bpc pencil_tile" keyed by device, CU
+ * count, grid, precision, block size and order is looked up first (no timing
+ * on a hit; a line without the pencil tile reads as tile 0) and appended after
+ * tuning.  ms_out (may be NULL) receives the chosen plane shapes'
+ * milliseconds per step for the forward and link passes (-1 on a cache hit).
+ * Synchronises. */
 mpe_status mpe_autotune(mpe_plan p, const void* psi, double dt, int32_t reps, const char* cache_path,
                         double* ms_out);
 
@@ -322,9 +333,11 @@ const char* mpe_noalloc_last_error(void);
  * Batched uneven systems: many independent eigenproblems (different grids,
  * state counts and potentials, one order and precision) advanced together.
  * Systems with the same grid share every propagation and H launch (one launch
- * per pass over all their states); overlaps, the small dense solve and the
- * rotation run per system; one iteration of all systems is one hipGraph
- * replay.  Results equal those of separate plans bitwise.
+ * per pass over all their states); the overlaps, small dense solves and
+ * rotations of all systems share one launch per kernel and tile class (see
+ * mpe_batch_set_batched_la); one iteration of all systems is one hipGraph
+ * replay.  Results equal those of separate plans bitwise.  Every system needs
+ * a grid with two-pass transforms (nx == ny), else MPE_ERR_UNSUPPORTED.
  * ------------------------------------------------------------------------- */
 typedef struct mpe_batch_s* mpe_batch;
 
@@ -354,6 +367,14 @@ mpe_status mpe_batch_iterate(mpe_batch b, void* const* psi, double dt, double* e
 
 /* Kernel launches in the captured iteration graph (diagnostic). */
 int32_t mpe_batch_launches_per_step(mpe_batch b);
+
+/* How mpe_batch_iterate issues the per-system linear algebra (overlaps,
+ * variances, small dense solves, eigenvector replays, rotations): on != 0 (the
+ * default) as one launch per kernel and 16-state tile class for all systems,
+ * each launch walking a device table of (system, chunk) work items; on == 0 as
+ * separate launches per system on parallel graph branches.  Results are bitwise
+ * identical either way. */
+mpe_status mpe_batch_set_batched_la(mpe_batch b, int32_t on);
 
 /* ---------------------------------------------------------------------------
  * Learned warm start (an addition outside the paper, whose Section III starts
@@ -409,6 +430,23 @@ mpe_status wsn_forward(wsn_net n, const float* v, float vscale, float yscale, in
  * (dL/dy); parameter gradients are ADDED to the accumulated ones.
  * MPE_ERR_STATE before any forward. */
 mpe_status wsn_backward(wsn_net n, const float* dy);
+
+/* One convolution layer alone (layer = 0..8 in parameter order c1a .. head),
+ * for checking each layer at its own shape.  info (wsn_layer_info) receives
+ * {ci, co, ci_pad, stride, relu}.  wsn_layer runs the layer's forward
+ *   y = act(conv(x) + b)     (act = ReLU unless the layer is the head)
+ * on x, device float32 channels-last [batch][din^3][ci_pad] (channels ci..
+ * ci_pad-1 zero), into y [batch][dout^3][co], dout = din / stride.  When dz is
+ * not NULL it holds dL/dy ([batch][dout^3][co]) and the backward follows: dz
+ * is overwritten by the pre-activation gradient, the layer's weight and bias
+ * gradients are ADDED to the accumulated ones (wsn_get_params which = 1), and,
+ * when dx is not NULL, dx [batch][din^3][ci] receives dL/dx.  The same bfloat16
+ * MFMA kernels as wsn_forward / wsn_backward.  MPE_ERR_INVALID_ARGUMENT for a
+ * bad layer, a batch outside [1, max_batch] or din not a multiple of
+ * 2 * stride. */
+mpe_status wsn_layer_info(wsn_net n, int32_t layer, int32_t* info);
+mpe_status wsn_layer(wsn_net n, int32_t layer, int32_t batch, int32_t din, const float* x, float* y, float* dz,
+                     float* dx);
 
 /* Adam step with bias correction (t = 1, 2, ...) on the accumulated
  * gradients, which it then clears. */

@@ -59,6 +59,8 @@ SIGNATURES = {
     "mpe_get_propagator": (_i32, [_vp]),
     "mpe_set_plane_shape": (C.c_int, [_vp, _i32, _i32, _i32]),
     "mpe_get_plane_shape": (C.c_int, [_vp, C.POINTER(_i32)]),
+    "mpe_set_pencil_shape": (C.c_int, [_vp, _i32]),
+    "mpe_get_pencil_shape": (_i32, [_vp]),
     "mpe_set_gemm_precision": (C.c_int, [_vp, _i32]),
     "mpe_autotune": (C.c_int, [_vp, _vp, C.c_double, _i32, C.c_char_p, _dp]),
     "mpe_set_graph": (C.c_int, [_vp, _i32]),
@@ -75,6 +77,7 @@ SIGNATURES = {
     "mpe_batch_step": (C.c_int, [_vp, C.POINTER(_vp), C.c_double]),
     "mpe_batch_iterate": (C.c_int, [_vp, C.POINTER(_vp), C.c_double, _dp, _dp, _dp, _dp]),
     "mpe_batch_launches_per_step": (C.c_int32, [_vp]),
+    "mpe_batch_set_batched_la": (C.c_int, [_vp, _i32]),
     "wsn_create": (C.c_int, [C.POINTER(_vp), _i32, _i32, _i32, C.c_uint64, _vp]),
     "wsn_destroy": (C.c_int, [_vp]),
     "wsn_last_error": (C.c_char_p, [_vp]),
@@ -84,6 +87,8 @@ SIGNATURES = {
     "wsn_zero_grads": (C.c_int, [_vp]),
     "wsn_forward": (C.c_int, [_vp, _vp, C.c_float, C.c_float, _i32, _vp]),
     "wsn_backward": (C.c_int, [_vp, _vp]),
+    "wsn_layer_info": (C.c_int, [_vp, _i32, C.POINTER(_i32)]),
+    "wsn_layer": (C.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp]),
     "wsn_adam_step": (C.c_int, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, _i32]),
     "wsn_subspace_loss": (C.c_int, [_vp, _vp, _vp, _i32, C.c_int64, _dp, _vp]),
     "wsn_procrustes_loss": (C.c_int, [_vp, _vp, _vp, _i32, C.c_int64, _dp, _vp]),

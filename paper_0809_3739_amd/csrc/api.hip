@@ -172,6 +172,7 @@ struct mpe_plan_s {
   // work-groups per CU); shape_ver counts changes so a captured graph can notice them
   int pmode[2] = {0, 0};
   int pbpc[2] = {0, 0};
+  int ptile = 0;               // pencil work-group shape (PencilArgs::tile)
   int shape_ver = 0;
   int n_cu = 0;
   int gemm = 0;                 // overlap GEMMs: 0 = float64 MFMA, 1 = float32 MFMA (float32 plans)
@@ -328,6 +329,7 @@ PlaneArgs plane_base(mpe_plan p) {
 PencilArgs pencil_base(mpe_plan p, void* data, const void* tab) {
   PencilArgs a;
   std::memset(&a, 0, sizeof(a));
+  a.tile = p->ptile;
   a.data = data;
   a.rz = p->rz();
   a.tab = tab;
@@ -1265,6 +1267,16 @@ mpe_status mpe_set_gemm_precision(mpe_plan p, int32_t mode) {
   return MPE_OK;
 }
 
+mpe_status mpe_set_pencil_shape(mpe_plan p, int32_t tile) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  if (tile < 0 || tile > 2) return fail(p, MPE_ERR_INVALID_ARGUMENT, "tile must be 0, 1 or 2");
+  p->ptile = tile;
+  p->shape_ver++;
+  return MPE_OK;
+}
+
+int32_t mpe_get_pencil_shape(mpe_plan p) { return p ? p->ptile : -1; }
+
 mpe_status mpe_get_plane_shape(mpe_plan p, int32_t* shape) {
   if (!p || !shape) return MPE_ERR_INVALID_ARGUMENT;
   shape[0] = p->pmode[0];
@@ -1297,19 +1309,24 @@ mpe_status mpe_autotune(mpe_plan p, const void* psi, double dt, int32_t reps, co
     std::FILE* f = std::fopen(cache_path, "r");
     if (f) {
       char line[512];
-      int best[4];
+      int best[5] = {0, 0, 0, 0, 0};
       bool hit = false;
       while (std::fgets(line, sizeof line, f)) {
         char* bar = std::strchr(line, '|');
         if (!bar) continue;
         *bar = 0;
-        if (key == line && std::sscanf(bar + 1, "%d %d %d %d", &best[0], &best[1], &best[2], &best[3]) == 4)
-          hit = true;   // the last matching line wins
+        int v[5] = {0, 0, 0, 0, 0};
+        const int n = std::sscanf(bar + 1, "%d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4]);
+        if (key == line && n >= 4) {   // the last matching line wins; a missing fifth field is tile 0
+          hit = true;
+          std::memcpy(best, v, sizeof best);
+        }
       }
       std::fclose(f);
       if (hit) {
         mpe_status s = mpe_set_plane_shape(p, MPE_KC_PLANE_FWD, best[0], best[1]);
         if (s == MPE_OK) s = mpe_set_plane_shape(p, MPE_KC_PLANE_LINK, best[2], best[3]);
+        if (s == MPE_OK) s = mpe_set_pencil_shape(p, best[4]);
         if (s == MPE_OK) {
           if (ms_out) ms_out[0] = ms_out[1] = -1.0;
           return MPE_OK;
@@ -1355,6 +1372,30 @@ mpe_status mpe_autotune(mpe_plan p, const void* psi, double dt, int32_t reps, co
   p->pbpc[0] = cand[best_c[0]][1];
   p->pmode[1] = cand[best_c[1]][0];
   p->pbpc[1] = cand[best_c[1]][1];
+  // pencil work-group shapes, timed with the chosen plane shapes
+  {
+    double best_pm = 1e300;
+    int best_t = 0;
+    p->prof = true;
+    for (int tile = 0; tile < 3 && s == MPE_OK; ++tile) {
+      p->ptile = tile;
+      s = enqueue_step(p, psi, p->phi);   // warm-up
+      if (s != MPE_OK) break;
+      collect_times(p);
+      for (int i = 0; i < MPE_KC_COUNT; ++i) p->kms[i] = 0, p->kcount[i] = 0;
+      for (int r = 0; r < reps && s == MPE_OK; ++r) s = enqueue_step(p, psi, p->phi);
+      collect_times(p);
+      if (p->kms[MPE_KC_PENCIL] < best_pm) best_pm = p->kms[MPE_KC_PENCIL], best_t = tile;
+    }
+    for (int i = 0; i < MPE_KC_COUNT; ++i) p->kms[i] = saved_ms[i], p->kcount[i] = saved_n[i];
+    p->prof = prof0;
+    p->ptile = best_t;
+    if (s != MPE_OK) {
+      p->ptile = 0;
+      p->shape_ver++;
+      return s;
+    }
+  }
   p->shape_ver++;
   if (ms_out) {
     ms_out[0] = best_ms[0] / reps;
@@ -1363,7 +1404,8 @@ mpe_status mpe_autotune(mpe_plan p, const void* psi, double dt, int32_t reps, co
   if (cache_path && *cache_path) {
     std::FILE* f = std::fopen(cache_path, "a");
     if (f) {
-      std::fprintf(f, "%s|%d %d %d %d\n", key.c_str(), p->pmode[0], p->pbpc[0], p->pmode[1], p->pbpc[1]);
+      std::fprintf(f, "%s|%d %d %d %d %d\n", key.c_str(), p->pmode[0], p->pbpc[0], p->pmode[1], p->pbpc[1],
+                   p->ptile);
       std::fclose(f);
     }
   }
@@ -1424,9 +1466,22 @@ struct mpe_batch_s {
   int launches = 0;
   // branches of the captured iteration: the per-system overlaps, small dense
   // solves and rotations of different systems run on these streams side by side
+  // (used when per-system launches are selected)
   std::vector<hipStream_t> br;
   hipEvent_t ev_fork = nullptr;
   std::vector<hipEvent_t> ev_join;
+  // batched linear algebra: one launch per kernel (and tile class) for all systems
+  bool batched_la = true;
+  struct JobSet {
+    char* dev = nullptr;   // device job table
+    size_t bytes = 0;
+    int njobs = 0, nblocks = 0, nt = 0, mode = 0;
+  };
+  std::vector<JobSet> gram_sets, rot_sets;
+  JobSet red_gram, red_rh, var, sd, rep;
+  int max_mp = 16;
+  void* job_mem = nullptr;
+  size_t job_cap = 0;
 };
 
 namespace {
@@ -1475,6 +1530,189 @@ void fill_descs(mpe_batch b, BatchGroup& g, void* const* psi, bool step_inplace)
       g.h_h.push_back(e);
     }
   }
+}
+
+// Job tables of the batched linear algebra for the state blocks psi (one per
+// system), laid out in one device allocation (kept between calls, grown as needed).
+mpe_status build_jobs(mpe_batch b, void* const* psi) {
+  std::vector<std::vector<GramJob>> gj(3 * 9);     // [mode][nt]
+  std::vector<std::vector<RotateJob>> rj(9);
+  std::vector<ReduceJob> rg, rr;
+  std::vector<VarianceJob> vj;
+  std::vector<SmallDenseArgs> dj;
+  std::vector<ReplayJob> pj;
+  int brg = 0, brr = 0, bpj = 0;
+  std::vector<int> bg(3 * 9, 0), br(9, 0);
+  b->max_mp = 16;
+  for (int i = 0; i < b->count; ++i) {
+    mpe_plan p = b->plans[i];
+    const int nt = p->mp / 16;
+    b->max_mp = std::max(b->max_mp, p->mp);
+    long chunk;
+    const int nch = gram_chunks(p, &chunk);
+    const void* X[3] = {p->phi, p->phi, psi[i]};
+    const void* Y[3] = {p->phi, p->hphi, p->phi};
+    const int modes[3] = {GRAM_SELF, GRAM_UPPER, GRAM_FULL};
+    for (int k = 0; k < 3; ++k) {
+      GramJob g;
+      g.X = X[k];
+      g.Y = Y[k];
+      g.partials = p->partials + (size_t)k * nch * p->mp * p->mp;
+      g.N = p->N;
+      g.chunk = chunk;
+      g.m = p->m;
+      const int slot = modes[k] * 9 + nt;
+      g.block0 = bg[slot];
+      bg[slot] += nch;
+      gj[slot].push_back(g);
+    }
+    ReduceJob r1;
+    r1.in = p->partials;
+    r1.out = p->S();                        // S, Hs, M contiguous
+    r1.count = (long)p->mp * p->mp;
+    r1.nparts = nch;
+    r1.ncomp = 3;
+    r1.block0 = brg;
+    brg += (int)((r1.count + 63) / 64) * 3;
+    rg.push_back(r1);
+    VarianceJob v;
+    v.S = p->S();
+    v.M = p->Mm();
+    v.re = p->re();
+    v.re_perp = p->reperp();
+    v.m = p->m;
+    v.mp = p->mp;
+    vj.push_back(v);
+    SmallDenseArgs d;
+    std::memset(&d, 0, sizeof(d));
+    d.S = p->S();
+    d.Hs = p->Hs();
+    d.L = p->L();
+    d.rot = p->rot;
+    d.scratch = p->scratch();
+    d.C = p->C();
+    d.theta = p->theta();
+    d.status = p->status;
+    d.m = p->m;
+    d.mp = p->mp;
+    d.mode = SD_RR;
+    d.max_sweeps = p->max_sweeps;
+    d.tol = p->jacobi_tol;
+    d.pivot_tol = p->pivot_tol;
+    dj.push_back(d);
+    ReplayJob q;
+    q.d = d;
+    q.block0 = bpj;
+    bpj += (p->m + REPLAY_ROWS - 1) / REPLAY_ROWS;
+    pj.push_back(q);
+    long rchunk;
+    const int nrch = rot_chunks(p, &rchunk);
+    RotateJob t;
+    std::memset(&t, 0, sizeof(t));
+    t.r.Phi = p->phi;
+    t.r.HPhi = p->hphi;
+    t.r.C = p->C();
+    t.r.theta = p->theta();
+    t.r.Psi = psi[i];
+    t.r.HPsi = p->hphi;
+    t.r.res_partials = p->partials;
+    t.r.status = p->status;
+    t.r.N = p->N;
+    t.r.chunk = rchunk;
+    t.r.m = p->m;
+    t.r.mp = p->mp;
+    t.block0 = br[nt];
+    br[nt] += nrch;
+    rj[nt].push_back(t);
+    ReduceJob r2;
+    r2.in = p->partials;
+    r2.out = p->rh();
+    r2.count = p->mp;
+    r2.nparts = nrch;
+    r2.ncomp = 1;
+    r2.block0 = brr;
+    brr += (int)((r2.count + 63) / 64);
+    rr.push_back(r2);
+  }
+  // one host image of every table, then one upload
+  std::vector<char> img;
+  auto put = [&](mpe_batch_s::JobSet& js, const void* data, size_t bytes, int njobs, int nblocks) {
+    const size_t off = (img.size() + 255) / 256 * 256;
+    img.resize(off + bytes);
+    std::memcpy(img.data() + off, data, bytes);
+    js.dev = reinterpret_cast<char*>(off);   // offset until the allocation is known
+    js.bytes = bytes;
+    js.njobs = njobs;
+    js.nblocks = nblocks;
+  };
+  b->gram_sets.clear();
+  b->rot_sets.clear();
+  for (int mode = 0; mode < 3; ++mode)
+    for (int nt = 1; nt <= 8; ++nt) {
+      auto& v = gj[mode * 9 + nt];
+      if (v.empty()) continue;
+      mpe_batch_s::JobSet js;
+      put(js, v.data(), v.size() * sizeof(GramJob), (int)v.size(), bg[mode * 9 + nt]);
+      js.nt = nt;
+      js.mode = mode;
+      b->gram_sets.push_back(js);
+    }
+  for (int nt = 1; nt <= 8; ++nt) {
+    auto& v = rj[nt];
+    if (v.empty()) continue;
+    mpe_batch_s::JobSet js;
+    put(js, v.data(), v.size() * sizeof(RotateJob), (int)v.size(), br[nt]);
+    js.nt = nt;
+    b->rot_sets.push_back(js);
+  }
+  put(b->red_gram, rg.data(), rg.size() * sizeof(ReduceJob), (int)rg.size(), brg);
+  put(b->red_rh, rr.data(), rr.size() * sizeof(ReduceJob), (int)rr.size(), brr);
+  put(b->var, vj.data(), vj.size() * sizeof(VarianceJob), (int)vj.size(), (int)vj.size());
+  put(b->sd, dj.data(), dj.size() * sizeof(SmallDenseArgs), (int)dj.size(), (int)dj.size());
+  put(b->rep, pj.data(), pj.size() * sizeof(ReplayJob), (int)pj.size(), bpj);
+  if (img.size() > b->job_cap) {
+    if (b->job_mem) (void)hipFree(b->job_mem);
+    b->job_mem = nullptr;
+    b->job_cap = 0;
+    BHIPCHK(b, hipMalloc(&b->job_mem, img.size()));
+    b->job_cap = img.size();
+  }
+  auto fix = [&](mpe_batch_s::JobSet& js) { js.dev = static_cast<char*>(b->job_mem) + reinterpret_cast<size_t>(js.dev); };
+  for (auto& js : b->gram_sets) fix(js);
+  for (auto& js : b->rot_sets) fix(js);
+  for (auto* js : {&b->red_gram, &b->red_rh, &b->var, &b->sd, &b->rep}) fix(*js);
+  BHIPCHK(b, hipMemcpyAsync(b->job_mem, img.data(), img.size(), hipMemcpyHostToDevice, b->st));
+  BHIPCHK(b, hipStreamSynchronize(b->st));   // the host image goes out of scope
+  return MPE_OK;
+}
+
+// Overlaps, variances, small dense solves, replays and rotations of every
+// system, batched: one launch per kernel and tile class.
+mpe_status enqueue_batch_la(mpe_batch b, hipStream_t st) {
+  for (auto& js : b->gram_sets) {
+    BHIPCHK(b, launch_gram_jobs(b->dbl, js.nt, js.mode, reinterpret_cast<const GramJob*>(js.dev), js.njobs,
+                                js.nblocks, st));
+    ++b->launches;
+  }
+  BHIPCHK(b, launch_reduce_jobs(reinterpret_cast<const ReduceJob*>(b->red_gram.dev), b->red_gram.njobs,
+                                b->red_gram.nblocks, st));
+  BHIPCHK(b, launch_variance_jobs(reinterpret_cast<const VarianceJob*>(b->var.dev), b->var.njobs, st));
+  BHIPCHK(b, launch_small_dense_jobs(reinterpret_cast<const SmallDenseArgs*>(b->sd.dev), b->sd.njobs, b->max_mp, st));
+  BHIPCHK(b, launch_replay_jobs(reinterpret_cast<const ReplayJob*>(b->rep.dev), b->rep.njobs, b->rep.nblocks, st));
+  b->launches += 4;
+  for (auto& js : b->rot_sets) {
+    BHIPCHK(b, launch_rotate_jobs(b->dbl, true, js.nt, reinterpret_cast<const RotateJob*>(js.dev), js.njobs,
+                                  js.nblocks, st));
+    ++b->launches;
+  }
+  BHIPCHK(b, launch_reduce_jobs(reinterpret_cast<const ReduceJob*>(b->red_rh.dev), b->red_rh.njobs,
+                                b->red_rh.nblocks, st));
+  ++b->launches;
+  for (int i = 0; i < b->count; ++i) {
+    mpe_plan p = b->plans[i];
+    BHIPCHK(b, hipMemcpyAsync(p->host_res, p->res, p->res_bytes, hipMemcpyDeviceToHost, st));
+  }
+  return MPE_OK;
 }
 
 mpe_status upload_descs(mpe_batch b) {
@@ -1557,6 +1795,7 @@ mpe_status enqueue_batch_iterate(mpe_batch b, void* const* psi, hipStream_t st) 
     mpe_status s = enqueue_group_h(b, g, st);
     if (s != MPE_OK) return s;
   }
+  if (b->batched_la) return enqueue_batch_la(b, st);
   // fork: system i's chain goes to branch i % nbr
   const int nbr = (int)b->br.size();
   if (nbr > 0) {
@@ -1607,6 +1846,7 @@ mpe_status mpe_batch_destroy(mpe_batch b) {
   }
   for (auto p : b->plans)
     if (p) mpe_plan_destroy(p);
+  if (b->job_mem) (void)hipFree(b->job_mem);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->gst) (void)hipStreamDestroy(b->gst);
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
@@ -1694,6 +1934,13 @@ const char* mpe_batch_last_error(mpe_batch b) { return b ? b->err.c_str() : "nul
 
 int32_t mpe_batch_launches_per_step(mpe_batch b) { return b ? b->launches : -1; }
 
+mpe_status mpe_batch_set_batched_la(mpe_batch b, int32_t on) {
+  if (!b) return MPE_ERR_INVALID_ARGUMENT;
+  b->batched_la = on != 0;
+  batch_drop_graph(b);
+  return MPE_OK;
+}
+
 mpe_status mpe_batch_step(mpe_batch b, void* const* psi, double dt) {
   if (!b || !psi) return MPE_ERR_INVALID_ARGUMENT;
   if (!(dt > 0.0) || !std::isfinite(dt)) return bfail(b, MPE_ERR_INVALID_ARGUMENT, "dt must be positive");
@@ -1709,10 +1956,12 @@ mpe_status mpe_batch_step(mpe_batch b, void* const* psi, double dt) {
   for (auto& g : b->groups) fill_descs(b, g, psi, true);
   mpe_status s = upload_descs(b);
   if (s != MPE_OK) return s;
+  const int keep = b->launches;   // the count reported is the iteration graph's
   for (auto& g : b->groups) {
     s = enqueue_group_step(b, g, b->st);
     if (s != MPE_OK) return s;
   }
+  b->launches = keep;
   BHIPCHK(b, hipStreamSynchronize(b->st));
   return MPE_OK;
 }
@@ -1735,6 +1984,7 @@ mpe_status mpe_batch_iterate(mpe_batch b, void* const* psi, double dt, double* e
     batch_drop_graph(b);
     for (auto& g : b->groups) fill_descs(b, g, psi, false);
     mpe_status s = upload_descs(b);
+    if (s == MPE_OK && b->batched_la) s = build_jobs(b, psi);
     if (s != MPE_OK) return s;
     BHIPCHK(b, hipStreamBeginCapture(b->gst, hipStreamCaptureModeRelaxed));
     s = enqueue_batch_iterate(b, psi, b->gst);

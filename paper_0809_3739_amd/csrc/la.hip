@@ -73,8 +73,10 @@ __device__ __forceinline__ void tile_coords(int u, int nt, bool sym, int& ti, in
   tj = ti + u;
 }
 
+// One chunk of points [p_begin, p_end) of X Y^T into out (mp x mp float64).
 template <typename F, int NT, int MODE>
-__global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
+__device__ __forceinline__ void gram_chunk(const F* __restrict__ X, const F* __restrict__ Y, int m, long N,
+                                           long p_begin, long p_end, double* __restrict__ out) {
   constexpr bool ONE = MODE == GRAM_SELF, TRI = MODE != GRAM_FULL;
   constexpr int mp = NT * 16;
   constexpr int TPW = GramTiles<NT, TRI>::per_wave;
@@ -82,13 +84,6 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
   constexpr int PER = (mp * GSLAB + 255) / 256;   // staged elements per thread and array
   __shared__ double xs[GSLAB][GLD];
   __shared__ double ys[ONE ? 1 : GSLAB][ONE ? 1 : GLD];
-  const int prod = blockIdx.y;
-  const F* __restrict__ X = reinterpret_cast<const F*>(g.X[prod]);
-  const F* __restrict__ Y = reinterpret_cast<const F*>(g.Y[prod]);
-  const int m = g.m;
-  const long N = g.N;
-  const long p_begin = (long)blockIdx.x * g.chunk;
-  const long p_end = min(N, p_begin + g.chunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   int tiv[TPW], tjv[TPW];
@@ -143,7 +138,6 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
     }
     __syncthreads();
   }
-  double* out = g.partials + ((long)prod * gridDim.x + blockIdx.x) * (long)mp * mp;
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     if (wave + 4 * t < NTILE) {
@@ -155,6 +149,40 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
       }
     }
   }
+}
+
+template <typename F, int NT, int MODE>
+__global__ __launch_bounds__(256) void gram_partial_kernel(GramArgs g) {
+  const int prod = blockIdx.y;
+  const long p_begin = (long)blockIdx.x * g.chunk;
+  gram_chunk<F, NT, MODE>(reinterpret_cast<const F*>(g.X[prod]), reinterpret_cast<const F*>(g.Y[prod]), g.m, g.N,
+                          p_begin, min(g.N, p_begin + g.chunk),
+                          g.partials + ((long)prod * gridDim.x + blockIdx.x) * (long)(NT * 16) * (NT * 16));
+}
+
+// Job-table lookup for batched launches: the job whose first work-group is the
+// largest one not above this work-group (jobs sorted by block0).
+template <typename J>
+__device__ __forceinline__ const J& find_job(const J* __restrict__ jobs, int njobs) {
+  int lo = 0, hi = njobs - 1;
+  const int b = (int)blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return jobs[lo];
+}
+
+// Many systems' overlap products of one tile class in one launch: each job is
+// one product of one system, its chunks consecutive work-groups.
+template <typename F, int NT, int MODE>
+__global__ __launch_bounds__(256) void gram_jobs_kernel(const GramJob* __restrict__ jobs, int njobs) {
+  const GramJob& J = find_job(jobs, njobs);
+  const int c = (int)blockIdx.x - J.block0;
+  const long p_begin = (long)c * J.chunk;
+  gram_chunk<F, NT, MODE>(reinterpret_cast<const F*>(J.X), reinterpret_cast<const F*>(J.Y), J.m, J.N, p_begin,
+                          min(J.N, p_begin + J.chunk), J.partials + (long)c * (NT * 16) * (NT * 16));
 }
 
 // Float32-MFMA variant for float32 states (the precision split of the overlap
@@ -387,12 +415,11 @@ __global__ __launch_bounds__(512) void gramb_partial_kernel(GramArgs g) {
 // q = w, w + RD_SLICES, ... of its lane's element, then the slices are added
 // in slice order (a fixed order for every call).
 constexpr int RD_SLICES = 8;
-__global__ __launch_bounds__(64 * RD_SLICES) void reduce_kernel(const double* __restrict__ in, int nparts, long count,
-                                                                double* __restrict__ out) {
+__device__ __forceinline__ void reduce_block(const double* __restrict__ in, int nparts, long count,
+                                             double* __restrict__ out, long e0, int c) {
   __shared__ double part[RD_SLICES][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const long e = (long)blockIdx.x * 64 + lane;
-  const int c = blockIdx.y;
+  const long e = e0 + lane;
   double s = 0.0;
   if (e < count) {
     const double* src = in + (long)c * nparts * count + e;
@@ -407,6 +434,19 @@ __global__ __launch_bounds__(64 * RD_SLICES) void reduce_kernel(const double* __
     for (int k = 1; k < RD_SLICES; ++k) t += part[k][lane];
     out[(long)c * count + e] = t;
   }
+}
+
+__global__ __launch_bounds__(64 * RD_SLICES) void reduce_kernel(const double* __restrict__ in, int nparts, long count,
+                                                                double* __restrict__ out) {
+  reduce_block(in, nparts, count, out, (long)blockIdx.x * 64, blockIdx.y);
+}
+
+// Many reductions in one launch: job j covers ceil(count / 64) * ncomp work-groups.
+__global__ __launch_bounds__(64 * RD_SLICES) void reduce_jobs_kernel(const ReduceJob* __restrict__ jobs, int njobs) {
+  const ReduceJob& J = find_job(jobs, njobs);
+  const int b = (int)blockIdx.x - J.block0;
+  const int per = (int)((J.count + 63) / 64);
+  reduce_block(J.in, J.nparts, J.count, J.out, (long)(b % per) * 64, b / per);
 }
 
 // ------------------------------------------------------------------ small dense problem
@@ -463,7 +503,7 @@ __device__ void mfma_product(int mp, PA P, QA Q, OUT out) {
   }
 }
 
-__global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs d) {
+__device__ __forceinline__ void small_dense_body(const SmallDenseArgs& d) {
   extern __shared__ double sh[];  // mp x LD
   __shared__ double red[20];
   __shared__ int flag;
@@ -739,6 +779,14 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
   stamp(d, 4);
 }
 
+__global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs d) { small_dense_body(d); }
+
+// Many systems' small dense solves in one launch: work-group i solves system i
+// (dynamic LDS sized for the largest block of the launch).
+__global__ __launch_bounds__(SD_THREADS) void small_dense_jobs_kernel(const SmallDenseArgs* __restrict__ jobs) {
+  small_dense_body(jobs[blockIdx.x]);
+}
+
 // Eigenvector replay: row r of C (holding W = L^-T) becomes W_r J_1 J_2 ... J_G
 // with the Jacobi rotations of the log, columns then permuted to ascending
 // Ritz values.  Rows are independent: one wavefront per row, 4 rows per
@@ -746,7 +794,7 @@ __global__ __launch_bounds__(SD_THREADS) void small_dense_kernel(SmallDenseArgs 
 // Lane l carries row elements l and l + 64; in step s of the round-robin
 // ordering it needs the partner element of each and the pair index k that
 // holds the (c, s) of that pair in the log.
-constexpr int RP_ROWS = 4, RP_CHUNK = 24;
+constexpr int RP_ROWS = REPLAY_ROWS, RP_CHUNK = 24;
 
 __device__ __forceinline__ void rr_partner(int e, int step, int n, int half, int& k, int& f) {
   if (e == 0) {           // pair 0 is (0, step + 1)
@@ -772,14 +820,14 @@ __device__ __forceinline__ void rr_partner(int e, int step, int n, int half, int
   }
 }
 
-__global__ __launch_bounds__(64 * RP_ROWS) void sd_replay_kernel(SmallDenseArgs d) {
+__device__ __forceinline__ void sd_replay_rows(const SmallDenseArgs& d, int rb) {
   __shared__ double lgbuf[RP_CHUNK * SD_LOG_STRIDE];
   __shared__ double rowv[RP_ROWS][MAXM];
   if (d.status[0] != ST_OK) return;   // uniform
   const int m = d.m, mp = d.mp, n = (m + 1) & ~1, half = n / 2;
   const int G = d.status[1] * (n - 1);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int r = blockIdx.x * RP_ROWS + w;
+  const int r = rb * RP_ROWS + w;
   const bool act = r < m;
   double* ur = rowv[w];
   const int e0 = lane, e1 = lane + 64;
@@ -823,7 +871,15 @@ __global__ __launch_bounds__(64 * RP_ROWS) void sd_replay_kernel(SmallDenseArgs 
     if (e0 < m) d.C[(long)r * mp + rank[e0]] = u0;
     if (e1 < m) d.C[(long)r * mp + rank[e1]] = u1;
   }
-  if (blockIdx.x == 0) stamp(d, 5);
+  if (rb == 0) stamp(d, 5);
+}
+
+__global__ __launch_bounds__(64 * RP_ROWS) void sd_replay_kernel(SmallDenseArgs d) { sd_replay_rows(d, blockIdx.x); }
+
+// Many systems' replays in one launch: job j covers ceil(m_j / RP_ROWS) work-groups.
+__global__ __launch_bounds__(64 * RP_ROWS) void sd_replay_jobs_kernel(const ReplayJob* __restrict__ jobs, int njobs) {
+  const ReplayJob& J = find_job(jobs, njobs);
+  sd_replay_rows(J.d, (int)blockIdx.x - J.block0);
 }
 
 // ------------------------------------------------------------------ rotation + residual epilogue
@@ -853,9 +909,9 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// Chunk c of the points (work-group of 256 threads).
 template <typename F, typename MT, bool WITH_H, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) == 4 ? 2 : 1))) void rotate_kernel(
-    RotateArgs r) {
+__device__ __forceinline__ void rotate_chunk(const RotateArgs& r, int c) {
   // C in LDS.  float32: row-major, rows padded by 16 words so that the two
   // 16-lane row segments of one ds_read land in disjoint banks.  float64:
   // transposed (cs[j * mp + i] = C[i][j]), measured faster for the 64-bit reads.
@@ -893,7 +949,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) 
 #pragma unroll
     for (int q = 0; q < 4; ++q) res[t][q] = 0.f;
 
-  const long p_begin = (long)blockIdx.x * r.chunk;
+  const long p_begin = (long)c * r.chunk;
   const long p_end = min(N, p_begin + r.chunk);
   for (long p0 = p_begin + 16 * wave; p0 < p_end; p0 += 64) {
     const long p = p0 + (lane & 15);
@@ -987,8 +1043,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) 
   __syncthreads();
   for (int j = tid; j < mp; j += 256) {
     const double v = rs[0][j] + rs[1][j] + rs[2][j] + rs[3][j];
-    r.res_partials[(long)blockIdx.x * mp + j] = v;
+    r.res_partials[(long)c * mp + j] = v;
   }
+}
+
+template <typename F, typename MT, bool WITH_H, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) == 4 ? 2 : 1))) void rotate_kernel(
+    RotateArgs r) {
+  rotate_chunk<F, MT, WITH_H, NT>(r, (int)blockIdx.x);
+}
+
+// Many systems' rotations of one tile class in one launch (one job per system).
+template <typename F, typename MT, bool WITH_H, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) == 4 ? 2 : 1))) void rotate_jobs_kernel(
+    const RotateJob* __restrict__ jobs, int njobs) {
+  const RotateJob& J = find_job(jobs, njobs);
+  rotate_chunk<F, MT, WITH_H, NT>(J.r, (int)blockIdx.x - J.block0);
 }
 
 // ------------------------------------------------------------------ small helpers
@@ -1011,6 +1081,22 @@ __global__ void variance_kernel(const double* S, const double* M, int m, int mp,
   }
   re[j] = sjj - mjj * mjj;
   re_perp[j] = sjj - s2;
+}
+
+// Many systems' variances in one launch: work-group j handles job j (m <= 128).
+__global__ void variance_jobs_kernel(const VarianceJob* __restrict__ jobs) {
+  const VarianceJob& J = jobs[blockIdx.x];
+  const int j = threadIdx.x;
+  if (j >= J.m) return;
+  const double sjj = J.S[(long)j * J.mp + j];
+  const double mjj = J.M[(long)j * J.mp + j];
+  double s2 = 0.0;
+  for (int i = 0; i < J.m; ++i) {
+    const double v = J.M[(long)i * J.mp + j];
+    s2 += v * v;
+  }
+  J.re[j] = sjj - mjj * mjj;
+  J.re_perp[j] = sjj - s2;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1132,8 +1218,92 @@ hipError_t launch_reduce(const double* in, int nparts, long count, int ncomp, do
 }
 
 hipError_t prepare_small_dense() {
-  return hipFuncSetAttribute((const void*)small_dense_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)((size_t)MAXM * (MAXM + 1) * sizeof(double)));
+  const int lds = (int)((size_t)MAXM * (MAXM + 1) * sizeof(double));
+  hipError_t e = hipFuncSetAttribute((const void*)small_dense_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)small_dense_jobs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+// ---- batched launchers
+template <typename F, int MODE>
+static hipError_t launch_gram_jobs_t(int nt, const GramJob* jobs, int njobs, int nblocks, hipStream_t st) {
+  dim3 grid(nblocks), block(256);
+  switch (nt) {
+    case 1: hipLaunchKernelGGL((gram_jobs_kernel<F, 1, MODE>), grid, block, 0, st, jobs, njobs); break;
+    case 2: hipLaunchKernelGGL((gram_jobs_kernel<F, 2, MODE>), grid, block, 0, st, jobs, njobs); break;
+    case 3: hipLaunchKernelGGL((gram_jobs_kernel<F, 3, MODE>), grid, block, 0, st, jobs, njobs); break;
+    case 4: hipLaunchKernelGGL((gram_jobs_kernel<F, 4, MODE>), grid, block, 0, st, jobs, njobs); break;
+    case 5: hipLaunchKernelGGL((gram_jobs_kernel<F, 5, MODE>), grid, block, 0, st, jobs, njobs); break;
+    case 6: hipLaunchKernelGGL((gram_jobs_kernel<F, 6, MODE>), grid, block, 0, st, jobs, njobs); break;
+    case 7: hipLaunchKernelGGL((gram_jobs_kernel<F, 7, MODE>), grid, block, 0, st, jobs, njobs); break;
+    case 8: hipLaunchKernelGGL((gram_jobs_kernel<F, 8, MODE>), grid, block, 0, st, jobs, njobs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_jobs(int is_double, int nt, int mode, const GramJob* jobs, int njobs, int nblocks,
+                            hipStream_t st) {
+  if (njobs <= 0 || nblocks <= 0) return hipSuccess;
+  if (is_double)
+    return mode == GRAM_SELF    ? launch_gram_jobs_t<double, GRAM_SELF>(nt, jobs, njobs, nblocks, st)
+           : mode == GRAM_UPPER ? launch_gram_jobs_t<double, GRAM_UPPER>(nt, jobs, njobs, nblocks, st)
+                                : launch_gram_jobs_t<double, GRAM_FULL>(nt, jobs, njobs, nblocks, st);
+  return mode == GRAM_SELF    ? launch_gram_jobs_t<float, GRAM_SELF>(nt, jobs, njobs, nblocks, st)
+         : mode == GRAM_UPPER ? launch_gram_jobs_t<float, GRAM_UPPER>(nt, jobs, njobs, nblocks, st)
+                              : launch_gram_jobs_t<float, GRAM_FULL>(nt, jobs, njobs, nblocks, st);
+}
+
+template <typename F, typename MT, bool H>
+static hipError_t launch_rotate_jobs_t(int nt, const RotateJob* jobs, int njobs, int nblocks, hipStream_t st) {
+  dim3 grid(nblocks), block(256);
+  switch (nt) {
+    case 1: hipLaunchKernelGGL((rotate_jobs_kernel<F, MT, H, 1>), grid, block, 0, st, jobs, njobs); break;
+    case 2: hipLaunchKernelGGL((rotate_jobs_kernel<F, MT, H, 2>), grid, block, 0, st, jobs, njobs); break;
+    case 3: hipLaunchKernelGGL((rotate_jobs_kernel<F, MT, H, 3>), grid, block, 0, st, jobs, njobs); break;
+    case 4: hipLaunchKernelGGL((rotate_jobs_kernel<F, MT, H, 4>), grid, block, 0, st, jobs, njobs); break;
+    case 5: hipLaunchKernelGGL((rotate_jobs_kernel<F, MT, H, 5>), grid, block, 0, st, jobs, njobs); break;
+    case 6: hipLaunchKernelGGL((rotate_jobs_kernel<F, MT, H, 6>), grid, block, 0, st, jobs, njobs); break;
+    case 7: hipLaunchKernelGGL((rotate_jobs_kernel<F, MT, H, 7>), grid, block, 0, st, jobs, njobs); break;
+    case 8: hipLaunchKernelGGL((rotate_jobs_kernel<F, MT, H, 8>), grid, block, 0, st, jobs, njobs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rotate_jobs(int is_double, bool with_h, int nt, const RotateJob* jobs, int njobs, int nblocks,
+                              hipStream_t st) {
+  if (njobs <= 0 || nblocks <= 0) return hipSuccess;
+  if (is_double)
+    return with_h ? launch_rotate_jobs_t<double, double, true>(nt, jobs, njobs, nblocks, st)
+                  : launch_rotate_jobs_t<double, double, false>(nt, jobs, njobs, nblocks, st);
+  return with_h ? launch_rotate_jobs_t<float, float, true>(nt, jobs, njobs, nblocks, st)
+                : launch_rotate_jobs_t<float, float, false>(nt, jobs, njobs, nblocks, st);
+}
+
+hipError_t launch_reduce_jobs(const ReduceJob* jobs, int njobs, int nblocks, hipStream_t st) {
+  if (njobs <= 0 || nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_jobs_kernel, dim3(nblocks), dim3(64 * RD_SLICES), 0, st, jobs, njobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_dense_jobs(const SmallDenseArgs* jobs, int njobs, int max_mp, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  const size_t lds = (size_t)max_mp * (max_mp + 1) * sizeof(double);
+  hipLaunchKernelGGL(small_dense_jobs_kernel, dim3(njobs), dim3(SD_THREADS), lds, st, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_replay_jobs(const ReplayJob* jobs, int njobs, int nblocks, hipStream_t st) {
+  if (njobs <= 0 || nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sd_replay_jobs_kernel, dim3(nblocks), dim3(64 * RP_ROWS), 0, st, jobs, njobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_variance_jobs(const VarianceJob* jobs, int njobs, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(variance_jobs_kernel, dim3(njobs), dim3(MAXM), 0, st, jobs);
+  return hipGetLastError();
 }
 
 hipError_t launch_small_dense(const SmallDenseArgs& d, hipStream_t st) {

@@ -78,6 +78,47 @@ inline int rot_chunking(long N, long* chunk) {
   return (int)((N + c - 1) / c);
 }
 
+// Batched launches over many systems (job tables in device memory, sorted by
+// block0, the first work-group of each job).  The kernels run the same code per
+// chunk / system as the single-system launches, so results are bitwise equal.
+struct GramJob {       // one product X Y^T of one system: partials [chunk][mp][mp]
+  const void* X;
+  const void* Y;
+  double* partials;
+  long N, chunk;
+  int m, block0;
+};
+struct RotateJob {     // one system's rotation: its chunks are consecutive work-groups
+  RotateArgs r;
+  int block0;
+};
+struct ReduceJob {     // out[c][e] = sum_q in[c][q][e]: ceil(count / 64) * ncomp work-groups
+  const double* in;
+  double* out;
+  long count;
+  int nparts, ncomp, block0;
+};
+struct ReplayJob {     // eigenvector replay of one system: ceil(m / 4) work-groups
+  SmallDenseArgs d;
+  int block0;
+};
+struct VarianceJob {   // R^E and R^E_perp of one system (one work-group of 128 threads)
+  const double* S;
+  const double* M;
+  double* re;
+  double* re_perp;
+  int m, mp;
+};
+hipError_t launch_gram_jobs(int is_double, int nt, int mode, const GramJob* jobs, int njobs, int nblocks,
+                            hipStream_t st);
+hipError_t launch_rotate_jobs(int is_double, bool with_h, int nt, const RotateJob* jobs, int njobs, int nblocks,
+                              hipStream_t st);
+hipError_t launch_reduce_jobs(const ReduceJob* jobs, int njobs, int nblocks, hipStream_t st);
+hipError_t launch_small_dense_jobs(const SmallDenseArgs* jobs, int njobs, int max_mp, hipStream_t st);
+hipError_t launch_replay_jobs(const ReplayJob* jobs, int njobs, int nblocks, hipStream_t st);
+hipError_t launch_variance_jobs(const VarianceJob* jobs, int njobs, hipStream_t st);
+constexpr int REPLAY_ROWS = 4;   // rows of C per replay work-group
+
 hipError_t launch_gram(int is_double, const GramArgs& g, int nprod, int nchunks, hipStream_t st);
 // float32 states only: float32 MFMA, float64 slab sums and partials
 hipError_t launch_gram32(const GramArgs& g, int nprod, int nchunks, hipStream_t st);

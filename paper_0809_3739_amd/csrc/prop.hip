@@ -531,16 +531,17 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
 }
 
 // ------------------------------------------------------------------ pencil pass
-template <int NZ>
+// Columns per work-group: THREADS / T (the T lanes of a column transform).
+template <int NZ, int THREADS>
 struct PencilCols {
-  static constexpr int value = 256 / Plan<NZ>::T;
+  static constexpr int value = THREADS / Plan<NZ>::T;
 };
 
-template <typename F, int NZ, int KIND>
-__global__ __launch_bounds__(256) void pencil_kernel(PencilArgs a) {
+template <typename F, int NZ, int KIND, int THREADS = 256>
+__global__ __launch_bounds__(THREADS) void pencil_kernel(PencilArgs a) {
   using P = Plan<NZ>;
   constexpr int T = P::T, E = P::E;
-  constexpr int C = PencilCols<NZ>::value;
+  constexpr int C = PencilCols<NZ, THREADS>::value;
   constexpr int CP = C + 1;   // padded row: the T lanes of a column hit different banks
   __shared__ cx<F> lds[T > 1 ? NZ * CP : 1];
 
@@ -567,7 +568,7 @@ __global__ __launch_bounds__(256) void pencil_kernel(PencilArgs a) {
   }
   const F* tx = tab;
   const F* ty = tab + a.NXH;
-  for (int i = tid; i < NZ; i += 256) {
+  for (int i = tid; i < NZ; i += THREADS) {
     rz_s[i] = reinterpret_cast<const cx<F>*>(a.rz)[i];
     if constexpr (KIND == PK_EXP || KIND == PK_ADD) tz_s[i] = tab[a.NXH + a.NY + i];
   }
@@ -848,18 +849,37 @@ static hipError_t launch_plane_n(int mode, const PlaneArgs& a, int nz, int nstat
   return hipGetLastError();
 }
 
-template <typename F, int N>
-static hipError_t launch_pencil_n(int kind, const PencilArgs& a, int nstates, hipStream_t st) {
-  constexpr int C = PencilCols<N>::value;
-  dim3 grid((a.M + C - 1) / C, nstates);
+template <typename F, int N, int THREADS>
+static hipError_t launch_pencil_nt(int kind, const PencilArgs& a, int nstates, hipStream_t st) {
+  constexpr int C = PencilCols<N, THREADS>::value;
+  dim3 grid((a.M + C - 1) / C, nstates), block(THREADS);
   switch (kind) {
-    case PK_EXP: hipLaunchKernelGGL((pencil_kernel<F, N, PK_EXP>), grid, dim3(256), 0, st, a); break;
-    case PK_ADD: hipLaunchKernelGGL((pencil_kernel<F, N, PK_ADD>), grid, dim3(256), 0, st, a); break;
-    case PK_FFT_FWD: hipLaunchKernelGGL((pencil_kernel<F, N, PK_FFT_FWD>), grid, dim3(256), 0, st, a); break;
-    case PK_FFT_INV: hipLaunchKernelGGL((pencil_kernel<F, N, PK_FFT_INV>), grid, dim3(256), 0, st, a); break;
+    case PK_EXP: hipLaunchKernelGGL((pencil_kernel<F, N, PK_EXP, THREADS>), grid, block, 0, st, a); break;
+    case PK_ADD: hipLaunchKernelGGL((pencil_kernel<F, N, PK_ADD, THREADS>), grid, block, 0, st, a); break;
+    case PK_FFT_FWD: hipLaunchKernelGGL((pencil_kernel<F, N, PK_FFT_FWD, THREADS>), grid, block, 0, st, a); break;
+    case PK_FFT_INV: hipLaunchKernelGGL((pencil_kernel<F, N, PK_FFT_INV, THREADS>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// LDS of one pencil work-group: the transform's exchange rows plus the staged tables.
+template <typename F, int N, int THREADS>
+constexpr size_t pencil_lds() {
+  return (Plan<N>::T > 1 ? (size_t)N * (PencilCols<N, THREADS>::value + 1) : 1) * 2 * sizeof(F) +
+         (size_t)N * 3 * sizeof(F);
+}
+
+template <typename F, int N>
+static hipError_t launch_pencil_n(int kind, const PencilArgs& a, int nstates, hipStream_t st) {
+  // other tile shapes where the transform spans several lanes and the LDS fits
+  if constexpr (Plan<N>::T >= 2) {
+    if (a.tile == 1) return launch_pencil_nt<F, N, 128>(kind, a, nstates, st);
+    if constexpr (pencil_lds<F, N, 512>() <= 64 * 1024) {
+      if (a.tile == 2) return launch_pencil_nt<F, N, 512>(kind, a, nstates, st);
+    }
+  }
+  return launch_pencil_nt<F, N, 256>(kind, a, nstates, st);
 }
 
 bool plane_supported(int is_double, int nx, int ny) {

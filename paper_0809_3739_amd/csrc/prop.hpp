@@ -74,6 +74,7 @@ struct PencilArgs {
   int state0;
   int chain;                  // desc mode: chain of this launch
   int desc_tables;            // desc mode: 0 = exp tables of `chain`, 1 = additive tables
+  int tile;                   // work-group shape: 0 = 256 threads, 1 = 128, 2 = 512 (columns scale alike)
 };
 
 bool plane_supported(int is_double, int nx, int ny);

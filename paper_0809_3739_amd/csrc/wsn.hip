@@ -815,6 +815,31 @@ mpe_status wsn_backward(wsn_net n, const float* dy) {
   return MPE_OK;
 }
 
+mpe_status wsn_layer_info(wsn_net n, int32_t layer, int32_t* info) {
+  if (!n || !info || layer < 0 || layer >= (int)n->layers.size()) return MPE_ERR_INVALID_ARGUMENT;
+  const Layer& L = n->layers[layer];
+  info[0] = L.ci;
+  info[1] = L.co;
+  info[2] = L.ci_pad;
+  info[3] = L.stride;
+  info[4] = L.relu;
+  return MPE_OK;
+}
+
+mpe_status wsn_layer(wsn_net n, int32_t layer, int32_t batch, int32_t din, const float* x, float* y, float* dz,
+                     float* dx) {
+  if (!n || !x || !y) return MPE_ERR_INVALID_ARGUMENT;
+  if (layer < 0 || layer >= (int)n->layers.size()) return wfail(n, MPE_ERR_INVALID_ARGUMENT, "no such layer");
+  const Layer& L = n->layers[layer];
+  if (batch < 1 || batch > n->max_batch) return wfail(n, MPE_ERR_INVALID_ARGUMENT, "batch out of range");
+  if (din < 2 * L.stride || din % (2 * L.stride)) return wfail(n, MPE_ERR_INVALID_ARGUMENT, "bad grid size");
+  n->batch = batch;
+  WHIP(n, fwd(n, layer, x, L.ci_pad, 0, y, L.co, 0, din));
+  if (!dz) return MPE_OK;
+  WHIP(n, bwd(n, layer, dz, L.co, y, L.co, 0, x, L.ci_pad, 0, dx, L.ci, 0, din));
+  return MPE_OK;
+}
+
 mpe_status wsn_adam_step(wsn_net n, float lr, float beta1, float beta2, float eps, int32_t t) {
   if (!n || t < 1) return MPE_ERR_INVALID_ARGUMENT;
   const float c1 = 1.f - std::pow(beta1, (float)t), c2 = 1.f - std::pow(beta2, (float)t);

@@ -201,10 +201,15 @@ class Plan:
         (the last three for float32 plans; see mpe_set_gemm_precision)."""
         self._check(self.lib.mpe_set_gemm_precision(self.h, {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}[mode]))
 
+    def set_pencil_shape(self, tile: int):
+        """Pencil work-group shape: 0 = 256 threads, 1 = 128, 2 = 512 (see mpe_set_pencil_shape)."""
+        self._check(self.lib.mpe_set_pencil_shape(self.h, int(tile)))
+
     def plane_shape(self) -> dict:
         buf = (C.c_int32 * 4)()
         self._check(self.lib.mpe_get_plane_shape(self.h, buf))
-        return {"plane_fwd": (buf[0], buf[1]), "plane_link": (buf[2], buf[3])}
+        return {"plane_fwd": (buf[0], buf[1]), "plane_link": (buf[2], buf[3]),
+                "pencil_tile": int(self.lib.mpe_get_pencil_shape(self.h))}
 
     def autotune(self, psi: torch.Tensor, dt: float, reps: int = 2, cache: str | None = None) -> dict:
         """Pick the fastest plane-pass shapes (mpe_autotune); ``cache`` defaults to $MPE_TUNE_CACHE."""
@@ -301,6 +306,10 @@ class Batch:
             res.append({k: v[off:off + mi].copy() for k, v in out.items()})
             off += mi
         return res
+
+    def set_batched_la(self, on: bool):
+        """Per-system linear algebra as one launch per kernel for all systems (default) or per system."""
+        self._check(self.lib.mpe_batch_set_batched_la(self.h, 1 if on else 0))
 
     @property
     def launches_per_step(self) -> int:

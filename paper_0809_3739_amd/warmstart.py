@@ -132,6 +132,29 @@ class WarmStartNet:
         _need(dy, (getattr(self, "_batch", 0), self.n_out, d, d, d), "output gradient")
         self._check(self.lib.wsn_backward(self.h, _ptr(dy)))
 
+    def layer_info(self, layer: int) -> dict:
+        buf = (C.c_int32 * 5)()
+        self._check(self.lib.wsn_layer_info(self.h, int(layer), buf))
+        return dict(zip(("ci", "co", "ci_pad", "stride", "relu"), list(buf)))
+
+    def layer(self, layer: int, x: torch.Tensor, dz: torch.Tensor | None = None, want_dx: bool = False):
+        """One convolution layer alone (see wsn_layer): x [B, d, d, d, ci_pad] float32 on the
+        device -> y [B, d/s, d/s, d/s, co]; with dz (dL/dy, overwritten by the
+        pre-activation gradient) the backward too, returning (y, dx or None)."""
+        info = self.layer_info(layer)
+        B, d = int(x.shape[0]), int(x.shape[1])
+        _need(x, (B, d, d, d, info["ci_pad"]), "layer input")
+        do = d // info["stride"]
+        y = torch.empty((B, do, do, do, info["co"]), dtype=torch.float32, device=x.device)
+        dx = None
+        if dz is not None:
+            _need(dz, (B, do, do, do, info["co"]), "layer output gradient")
+            if want_dx:
+                dx = torch.empty((B, d, d, d, info["ci"]), dtype=torch.float32, device=x.device)
+        self._check(self.lib.wsn_layer(self.h, int(layer), B, d, _ptr(x), _ptr(y),
+                                       _ptr(dz) if dz is not None else None, _ptr(dx) if dx is not None else None))
+        return y, dx
+
     def adam_step(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
         self.t += 1
         self._check(self.lib.wsn_adam_step(self.h, lr, beta1, beta2, eps, self.t))

@@ -819,12 +819,16 @@ def test_order_study_runs(P):
     assert rows[2]["t2_per_state"] == rows[2]["state_propagations"] * 9 // 8
 
 
-def test_batch_matches_individual_plans(P):
+@pytest.mark.parametrize("batched_la", [True, False])
+def test_batch_matches_individual_plans(P, batched_la):
     """Uneven systems advanced as one batch equal separately planned systems bitwise
-    (batched propagation launches over several systems, one graph per iteration)."""
+    (batched propagation launches over several systems, the overlaps, small dense
+    solves and rotations of all systems in one launch per kernel and tile class or
+    per system, one graph per iteration)."""
     systems = [W.random_molecule(s, grids=(32, 48), n_states=(4, 12)) for s in (11, 12, 13, 14, 15)]
-    say("batch vs individual", [(sy.grid[0], sy.n_states) for sy in systems])
+    say("batch vs individual", [(sy.grid[0], sy.n_states) for sy in systems], "batched LA", batched_la)
     batch = P.Batch(systems, 8, "fp32")
+    batch.set_batched_la(batched_la)
     psis_b, plans, psis_i = [], [], []
     for i, sy in enumerate(systems):
         x0 = W.random_states(100 + i, sy.n_states, sy.grid)
@@ -845,13 +849,53 @@ def test_batch_matches_individual_plans(P):
             assert np.array_equal(outs[i]["eig"], r["eig"]), (it, i)
             assert np.array_equal(outs[i]["rh"], r["rh"]), (it, i)
             assert np.array_equal(psis_b[i].cpu().numpy(), psis_i[i].cpu().numpy()), (it, i)
-    say("  launches per batched iteration", batch.launches_per_step)
+    launches = batch.launches_per_step
+    say("  launches per batched iteration", launches)
     # the in-place batched step equals each plan's mpe_step
     for i, pl in enumerate(plans):
         pl.step(psis_i[i], 0.3)
     batch.step(psis_b, 0.3)
     for i in range(len(systems)):
         assert np.array_equal(psis_b[i].cpu().numpy(), psis_i[i].cpu().numpy())
+    if batched_la:
+        # two grids (24 propagation and H launches each at order 8) and the systems' linear
+        # algebra in a fixed number of launches, whatever the number of systems
+        assert launches <= 2 * 24 + 12
+
+
+@pytest.mark.timeout(600)
+def test_batch_iteration_matches_oracle(P):
+    """One batched iteration of uneven systems (grids 32, 64 and 96, up to 60 states,
+    float64 and float32 batches) against the oracle's iteration of each system:
+    Ritz values 1e-10 / 1e-6 and the subspace, as for single plans."""
+    specs = [(21, 32, 9), (22, 64, 60), (23, 96, 17), (24, 64, 5)]
+    systems = []
+    for seed, g, ns in specs:
+        sy = W.random_molecule(seed, grids=(g,), n_states=(ns, ns))
+        systems.append(sy)
+    for prec in ("fp64", "fp32"):
+        say("batch vs oracle", prec, [(sy.grid[0], sy.n_states) for sy in systems])
+        batch = P.Batch(systems, 8, prec)
+        refs, psis = [], []
+        for i, sy in enumerate(systems):
+            x, _, _ = oracle.cholesky_orthonormalize(W.random_states(200 + i, sy.n_states, sy.grid))
+            x = rounded(x, prec)
+            refs.append(x)
+            psis.append(batch.new_states(i, x))
+        outs = batch.iterate(psis, 0.25)
+        for i, sy in enumerate(systems):
+            r = oracle.iterate(refs[i], sy.V, 0.25, 4, sy.grid, sy.box)
+            m = sy.n_states
+            e = float(np.max(np.abs(outs[i]["eig"] - r.theta)) / np.max(np.abs(r.theta)))
+            G = psis[i].cpu().numpy().astype(np.float64).reshape(m, -1)
+            R = r.psi.reshape(m, -1)
+            proj = float(np.linalg.norm(R - (R @ G.T) @ G) / math.sqrt(m))
+            say(f"  system {i} grid {sy.grid[0]} states {m}: eig rel {e:.2e} subspace {proj:.2e}")
+            if prec == "fp64":
+                assert e < 1e-10 and proj < 1e-9
+            else:
+                assert e < 1e-6 and proj < 1e-4
+        batch.close()
 
 
 # ------------------------------------------------------------------ plane-pass launch shapes
@@ -876,6 +920,13 @@ def test_plane_shapes_are_bitwise_identical(P, prec, grid, ns, order):
         outs.append(x.cpu())
     for sh, o in zip(SHAPES[1:], outs[1:]):
         assert torch.equal(o, outs[0]), sh
+    plan.set_plane_shape("plane_fwd", 0, 0)
+    plan.set_plane_shape("plane_link", 0, 0)
+    for tile in (1, 2, 0):
+        plan.set_pencil_shape(tile)
+        x = psi0.clone()
+        plan.step(x, 0.3)
+        assert torch.equal(x.cpu(), outs[0]), ("pencil tile", tile)
     # the fused iteration (graph replay) after shape changes
     eigs = []
     for shape in [(0, 0), (1, 1), (2, 2), (3, 0), (5, 1)]:
