@@ -415,6 +415,7 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0, c
                a.fac_index = 2 * k + 1;
                a.real_out = out_k;
                a.state0 = s0;
+               a.states_fast = p->pmode[1] / 3;
                return launch_plane(p->dbl, PM_OUT, p->nx, a, p->nz, cnt, p->st);
              }, first));
     }
@@ -592,6 +593,7 @@ mpe_status run_h(mpe_plan p, const void* src, void* hdst, int first = 0) {
            c.fac = p->Vf;
            c.real_out = hdst;
            c.state0 = s0;
+           c.states_fast = p->pmode[1] / 3;   // the link pass's plane order
            return launch_plane(p->dbl, PM_HTAIL, p->nx, c, p->nz, cnt, p->st);
          }, first));
   toc(p, t);

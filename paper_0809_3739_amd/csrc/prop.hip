@@ -485,8 +485,8 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
       }
     }
   } else {  // PM_HTAIL, PM_OUT
-    const int z = blockIdx.x;
-    const Ptrs P = ptrs_of((long)blockIdx.y + a.state0);
+    const int z = a.states_fast ? blockIdx.y : blockIdx.x;
+    const Ptrs P = ptrs_of((long)(a.states_fast ? blockIdx.x : blockIdx.y) + a.state0);
     const long z_real = (long)z * plane_real, z_spec = (long)z * plane_spec;
     gp<cx<F>> spec = P.spec;
     gp<const F> facb = P.facb;
@@ -831,9 +831,9 @@ static hipError_t launch_plane_n(int mode, const PlaneArgs& a, int nz, int nstat
       return hipGetLastError();
     }
   }
-  // The H and single-chain passes walk z planes fastest; the forward and link
-  // passes take the order of PlaneArgs::states_fast; the tail pass walks states
-  // fastest, so the work-groups in flight share a few z planes and the 2K
+  // The forward, link, H-tail and single-chain passes take the order of
+  // PlaneArgs::states_fast; the fused tail pass always walks states fastest,
+  // so the work-groups in flight share a few z planes and the 2K
   // potential-factor planes they read stay in every XCD's L2 while the states
   // stream past
   dim3 grid(nz, nstates), grid_t(nstates, nz);
@@ -842,8 +842,8 @@ static hipError_t launch_plane_n(int mode, const PlaneArgs& a, int nz, int nstat
     case PM_FWD: hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD, 0>), grid_fl, block, 0, st, a); break;
     case PM_LINK: hipLaunchKernelGGL((plane_kernel<F, N, PM_LINK, 0>), grid_fl, block, 0, st, a); break;
     case PM_TAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_TAIL, 0>), grid_t, block, 0, st, a); break;
-    case PM_HTAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_HTAIL, 0>), grid, block, 0, st, a); break;
-    case PM_OUT: hipLaunchKernelGGL((plane_kernel<F, N, PM_OUT, 0>), grid, block, 0, st, a); break;
+    case PM_HTAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_HTAIL, 0>), grid_fl, block, 0, st, a); break;
+    case PM_OUT: hipLaunchKernelGGL((plane_kernel<F, N, PM_OUT, 0>), grid_fl, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

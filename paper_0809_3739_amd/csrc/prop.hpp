@@ -53,7 +53,7 @@ struct PlaneArgs {
   // work-group per CU (1) or of the one-plane launch (2)
   int persist_mode;
   int persist_blocks;
-  // PM_FWD / PM_LINK plane order: 0 = z planes fastest (neighbouring work-groups
+  // PM_FWD / PM_LINK / PM_HTAIL / PM_OUT plane order: 0 = z planes fastest (neighbouring work-groups
   // take neighbouring planes of one state), 1 = states fastest (the work-groups
   // in flight share a few z planes, so each factor-table plane is fetched into
   // an XCD's L2 once and read there by every state)

@@ -4,6 +4,15 @@
     python -m paper_0809_3739_amd.rocprof_summary traffic <fetch counter_collection.csv> \
         <write counter_collection.csv> <out.txt> "<fetch command>" "<write command>" \
         <kernel substring> <copy kernel substring> <copy bytes per dispatch (each way)>
+    python -m paper_0809_3739_amd.rocprof_summary mfma <counter_collection.csv> <kernel_trace.csv> <out.md> \
+        "<command>" "<title>"
+
+MFMA: per kernel, the mean over dispatches of SQ_INSTS_VALU_MFMA_MOPS_F32 / _F64
+(flops / 512, so flops = 512 x count); the achieved MFMA rate = flops over the
+dispatch's duration from the kernel trace of the same run, and its fraction of
+the dense peak of the operand type.  SQ_VALU_MFMA_BUSY_CYCLES is not used: on
+MI355X it reads as round multiples of 2^18 (2^30, 2^31 for millisecond kernels),
+not a cycle count.
 
 Traffic: rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE report KiB per dispatch
 (summed over the L2 channels).  Both are scaled by the factor that makes the
@@ -99,12 +108,52 @@ def read_traffic(path: str) -> float | None:
     return float(vals["bytes_per_launch"])
 
 
+def mfma(counters_csv: str, trace_csv: str, out: str, command: str, title: str) -> None:
+    per = {}
+    for r in csv.DictReader(open(counters_csv)):
+        k = r.get("Kernel_Name", "")
+        d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        per.setdefault(k, {}).setdefault(d, {})
+        c = r.get("Counter_Name")
+        per[k][d][c] = per[k][d].get(c, 0.0) + float(r["Counter_Value"])
+    dur = {}
+    for r in csv.DictReader(open(trace_csv)):
+        k = r.get("Kernel_Name", "")
+        ns = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+        dur.setdefault(k, []).append(ns)
+    lines = [f"# rocprofv3 MFMA counters: {title}", "", "Command (from the repository root, one MI355X):", "",
+             "```", command, "```", "",
+             "| kernel | dispatches | avg us | MFMA F32 GFLOP | MFMA F64 GFLOP | achieved TFLOP/s | % of peak |",
+             "|---|---|---|---|---|---|---|"]
+    rows = []
+    for k, ds in per.items():
+        vals = list(ds.values())
+        mean = lambda c: sum(v.get(c, 0.0) for v in vals) / len(vals)   # noqa: E731
+        f32 = mean("SQ_INSTS_VALU_MFMA_MOPS_F32") * 512
+        f64 = mean("SQ_INSTS_VALU_MFMA_MOPS_F64") * 512
+        if f32 + f64 <= 0:
+            continue
+        t = dur.get(k, [])
+        avg_us = sum(t) / len(t) / 1e3 if t else float("nan")
+        rate = (f32 + f64) / (avg_us * 1e-6) / 1e12 if t else float("nan")
+        util = 100.0 * rate / (157.3 * f32 / (f32 + f64) + 78.6 * f64 / (f32 + f64))
+        name = k.replace("void ", "").split("(")[0].strip()
+        rows.append((f32 + f64, f"| `{name}` | {len(vals)} | {avg_us:.1f} | {f32 / 1e9:.2f} | {f64 / 1e9:.2f} | "
+                                f"{rate:.1f} | {util:.1f} |"))
+    lines += [r for _, r in sorted(rows, reverse=True)]
+    lines += ["", "Peaks (dense, MI355X spec): float32 MFMA 157.3 TFLOP/s, float64 MFMA 78.6 TFLOP/s."]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     a = sys.argv[1:]
     if a and a[0] == "stats" and len(a) == 5:
         stats(*a[1:])
     elif a and a[0] == "traffic" and len(a) == 9:
         traffic(a[1], a[2], a[3], a[4], a[5], a[6], a[7], float(a[8]))
+    elif a and a[0] == "mfma" and len(a) == 6:
+        mfma(*a[1:])
     else:
         print(__doc__)
         sys.exit(2)

@@ -9,12 +9,13 @@ through the network, so the bars are those of one layer:
 * against the reference fed the kernels' bfloat16 operand roundings (inputs,
   weights and output gradients rounded to nearest-even bfloat16; the bias
   gradient sums the float32 output gradient): the two differ only in the order
-  and width of their accumulations (float32 on the GPU, float64 here), ~1e-6
-  relative by norm; bar 1e-4 per tensor;
+  and width of their accumulations (float32 on the GPU, float64 here):
+  measured <= 4.1e-7 relative by norm on MI355X; bar 2e-6 per tensor;
 * against the exact float64 layer: bfloat16 keeps 8 significant bits (unit
   roundoff 2^-9); each product rounds both operands and independent roundings
-  add in quadrature, so the relative error by norm is a few 1e-3; bar 2e-2
-  per tensor.
+  add in quadrature, so the relative error by norm is ~sqrt(2/3) 2^-9 = 2.3e-3
+  (measured 2.3e-3 to 2.4e-3); bar 5e-3 per tensor (the bias gradient, a plain
+  float32 sum, 2e-6).
 
 The backward uses the GPU forward's own ReLU mask (the pre-activation gradient
 is the output gradient times [y > 0], compared exactly), so each gradient is
@@ -103,5 +104,5 @@ def test_layer_matches_reference(net, li, d):
     for k, (e1, e2) in errs.items():
         say(f"  {k}: vs bf16 emulation {e1:.2e}  vs float64 {e2:.2e}")
     for k, (e1, e2) in errs.items():
-        assert e1 < 1e-4, (k, e1)
-        assert e2 < 2e-2, (k, e2)
+        assert e1 < 2e-6, (k, e1)
+        assert e2 < 5e-3, (k, e2)
