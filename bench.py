@@ -50,7 +50,7 @@ def prop_bytes_per_launch(kind: str, grid, m: int, K: int, fsz: int) -> dict:
     spec = nz * ny * (nx // 2 + 1) * 2 * fsz       # one half spectrum
     real = N * fsz                                  # one real state / table
     return {
-        "plane_fwd": m * (real + spec) + real,      # states in, spectra out, one factor table
+        "plane_fwd": m * (real + K * spec) + K * real,   # states in once, K chains' spectra out, K factor tables
         "pencil": m * 2 * spec,                     # in place
         "plane_link": m * 2 * spec + real,
         "plane_tail": m * (K * spec + real) + K * real,
@@ -58,7 +58,7 @@ def prop_bytes_per_launch(kind: str, grid, m: int, K: int, fsz: int) -> dict:
 
 
 def prop_launches_per_step(K: int) -> dict:
-    return {"plane_fwd": K, "pencil": K * (K + 1) // 2, "plane_link": K * (K - 1) // 2, "plane_tail": 1}
+    return {"plane_fwd": 1, "pencil": K * (K + 1) // 2, "plane_link": K * (K - 1) // 2, "plane_tail": 1}
 
 
 def cpu_baseline(s, K: int, fsz: int, budget_s: float = 15.0) -> dict:

@@ -357,19 +357,19 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0, c
   const size_t f = p->fsz;
   double c[MAX_K];
   mpe_coeffs(p->K, c);
-  for (int k = 1; k <= p->K; ++k) {
-    void* Wk = chain_spec(p, k - 1);
-    const int half = 2 * k - 1;   // table exp(-dt V / 2k)
-    const int full = k - 1;       // table exp(-dt V / k)
-    const void* ktab = (const char*)kin + (size_t)(k - 1) * (p->nxh + p->ny + p->nz) * f;
+  // every chain's first potential half-step exp(-dt V / 2k) (table 2k - 1) and
+  // forward transform, from one read of src
+  {
     Timer t;
     tic(p, t, MPE_KC_PLANE_FWD);
     HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
              PlaneArgs a = plane_base(p);
              a.real_in = src;
              a.fac = fac;
-             a.fac_index = half;
-             a.spec = Wk;
+             a.fac_index = 1;
+             a.fwd_chains = p->K;
+             a.spec = chain_spec(p, 0);
+             a.chain_stride = (long)p->m * p->spec;
              a.state0 = s0;
              a.persist_mode = p->pmode[0] % 3;
              a.states_fast = p->pmode[0] / 3;
@@ -377,6 +377,12 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0, c
              return launch_plane(p->dbl, PM_FWD, p->nx, a, p->nz, cnt, p->st);
            }, first));
     toc(p, t);
+  }
+  for (int k = 1; k <= p->K; ++k) {
+    void* Wk = chain_spec(p, k - 1);
+    const int full = k - 1;       // table exp(-dt V / k)
+    const void* ktab = (const char*)kin + (size_t)(k - 1) * (p->nxh + p->ny + p->nz) * f;
+    Timer t;
     for (int l = 1; l <= k; ++l) {
       tic(p, t, MPE_KC_PENCIL);
       HIPCHK(p, for_groups(p, [&](int s0, int cnt) {
@@ -1732,13 +1738,17 @@ mpe_status enqueue_group_step(mpe_batch b, BatchGroup& g, hipStream_t st) {
   mpe_plan p0 = b->plans[g.sys[0]];
   double c[MAX_K];
   mpe_coeffs(b->K, c);
-  for (int k = 1; k <= b->K; ++k) {
+  {
+    // every chain's first half-step and forward transform from one read of psi
     PlaneArgs a = plane_base(p0);
     a.desc = g.d_step;
-    a.chain = k - 1;
-    a.fac_index = 2 * k - 1;
+    a.chain = 0;
+    a.fac_index = 1;
+    a.fwd_chains = b->K;
     BHIPCHK(b, launch_plane(b->dbl, PM_FWD, g.nx, a, g.nz, g.nstates, st));
     ++b->launches;
+  }
+  for (int k = 1; k <= b->K; ++k) {
     for (int l = 1; l <= k; ++l) {
       PencilArgs pa = pencil_base(p0, nullptr, nullptr);
       pa.desc = g.d_step;

@@ -888,8 +888,6 @@ __global__ __launch_bounds__(64 * RP_ROWS) void sd_replay_jobs_kernel(const Repl
 // MT is the MFMA operand type: double (v_mfma_f64_16x16x4f64, float64 plans)
 // or float (v_mfma_f32_16x16x4f32, float32 plans: C rounded to float32, the
 // rotation of float32 states then loses nothing beyond float32 storage).
-// A strip's B operands are loaded in groups of KG k-steps, each group issued
-// before the MFMAs of the previous one.
 
 template <typename MT>
 struct Mfma;
@@ -951,50 +949,61 @@ __device__ __forceinline__ void rotate_chunk(const RotateArgs& r, int c) {
 
   const long p_begin = (long)c * r.chunk;
   const long p_end = min(N, p_begin + r.chunk);
-  for (long p0 = p_begin + 16 * wave; p0 < p_end; p0 += 64) {
+  // B operands in groups of KG k-steps; each group's loads are issued before
+  // the MFMAs of the group before it, across strip boundaries too (the next
+  // strip's first group is in flight while this strip's last MFMAs and its
+  // stores run), so a wave waits on HBM only for its very first group.
+  constexpr int KG = F32 ? (nk < 4 ? nk : 4) : 2;
+  constexpr int NG = (nk + KG - 1) / KG;
+  MT b[KG], bh[KG], nb[KG], nbh[KG];
+  // float32: unconditional loads (masked lanes read element 0 and discard it),
+  // so no exec-mask branches surround them; the k-step offsets 4 k N are
+  // wave-uniform.  float64 keeps predicated loads (measured faster there).
+  auto load_group = [&](long p0, int k0, MT (&x)[KG], MT (&xh)[KG]) {
     const long p = p0 + (lane & 15);
     const bool pok = p < p_end;
-    // B operands in groups of KG k-steps; the next group's loads are issued
-    // before the current group's MFMAs so their latency hides behind them.
-    constexpr int KG = sizeof(MT) == 4 ? 4 : 2;
-    MT b[KG], bh[KG], nb[KG], nbh[KG];
-    // float32: unconditional loads (masked lanes read element 0 and discard it),
-    // so no exec-mask branches surround them; the k-step offsets 4 k N are
-    // wave-uniform.  float64 keeps predicated loads (measured faster there).
     const long lane_off = (long)(lane >> 4) * N + p;
-    auto load_group = [&](int k0, MT (&x)[KG], MT (&xh)[KG]) {
 #pragma unroll
-      for (int kk = 0; kk < KG; ++kk) {
-        const int k = k0 + kk;
-        const bool ok = k < nk && pok && 4 * k + (lane >> 4) < m;
-        if constexpr (F32) {
-          const long idx = ok ? lane_off + (long)(4 * k) * N : 0;
-          const F v = Phi[idx];
-          x[kk] = ok ? (MT)v : MT(0);
-          if (WITH_H) {
-            const F vh = HPhi[idx];
-            xh[kk] = ok ? (MT)vh : MT(0);
-          } else {
-            xh[kk] = MT(0);
-          }
+    for (int kk = 0; kk < KG; ++kk) {
+      const int k = k0 + kk;
+      const bool ok = k < nk && pok && 4 * k + (lane >> 4) < m;
+      if constexpr (F32) {
+        const long idx = ok ? lane_off + (long)(4 * k) * N : 0;
+        const F v = Phi[idx];
+        x[kk] = ok ? (MT)v : MT(0);
+        if (WITH_H) {
+          const F vh = HPhi[idx];
+          xh[kk] = ok ? (MT)vh : MT(0);
         } else {
-          const long idx = lane_off + (long)(4 * k) * N;
-          x[kk] = ok ? (MT)Phi[idx] : MT(0);
-          xh[kk] = (WITH_H && ok) ? (MT)HPhi[idx] : MT(0);
+          xh[kk] = MT(0);
         }
+      } else {
+        const long idx = lane_off + (long)(4 * k) * N;
+        x[kk] = ok ? (MT)Phi[idx] : MT(0);
+        xh[kk] = (WITH_H && ok) ? (MT)HPhi[idx] : MT(0);
       }
-    };
-    load_group(0, b, bh);
+    }
+  };
+  const long p_first = p_begin + 16 * wave;
+  if (p_first < p_end) load_group(p_first, 0, b, bh);
+  for (long p0 = p_first; p0 < p_end; p0 += 64) {
+    const long p = p0 + (lane & 15);
+    const bool pok = p < p_end;
     acc_t ap[NT], ah[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) ap[t] = ah[t] = acc_t{0, 0, 0, 0};
 #pragma unroll 1
-    for (int k0 = 0; k0 < nk; k0 += KG) {
-      if (k0 + KG < nk) load_group(k0 + KG, nb, nbh);
+    for (int gq = 0; gq < NG; ++gq) {
+      if (gq + 1 < NG) {
+        load_group(p0, (gq + 1) * KG, nb, nbh);
+      } else if (p0 + 64 < p_end) {
+        load_group(p0 + 64, 0, nb, nbh);
+      }
+      const int k0 = gq * KG;
 #pragma unroll
       for (int kk = 0; kk < KG; ++kk) {
         const int k = k0 + kk;
-        if (KG <= nk || k < nk) {
+        if (KG * NG == nk || k < nk) {
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
             // A (16x4) = C^T tile: A[jj][kk] = C[4k + kk][t*16 + jj]

@@ -292,33 +292,56 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
   };
 
   if constexpr (MODE == PM_FWD || MODE == PM_LINK) {
-    // Planes of this work-group: one (z, state) pair, or with PERSIST every
-    // gridDim.x-th plane of the launch; the next plane's input (rows for the
-    // forward pass, spectrum columns for the link pass) is loaded while the
-    // current plane is transformed.
-    const long nplanes = PERSIST ? (long)a.nz * a.nstates : 1;
-    long p = PERSIST ? (long)blockIdx.x : 0;
-    // (a persistent launch has at most nplanes work-groups: p < nplanes here)
-    auto locate = [&](long q, int& zq, Ptrs& Pq) {
+    // Work items of this work-group: one (chain, z, state) item, or with
+    // PERSIST every gridDim.x-th item of the launch; the next item's input
+    // (rows for the forward pass, spectrum columns for the link pass) is
+    // loaded while the current plane is transformed.
+    // A forward launch can form several chains (fwd_chains) from each plane of
+    // rows.  The chains of one plane run on work-groups of one XCD (work-group
+    // w runs on XCD w mod 8), so the plane comes from HBM once and from that
+    // XCD's L2 for the other chains: item w is chain (w / 8) mod nch of plane
+    // index 8 (w / 8 nch) + w mod 8, plane indices padded to a multiple of 8
+    // (the padding is skipped).  With one chain the item is the plane index.
+    // The plane index runs over the (z, state) pairs with z or states fastest.
+    const int nch = (MODE == PM_FWD && a.fwd_chains > 1) ? a.fwd_chains : 1;
+    const long nplanes = (long)a.nz * a.nstates;
+    const long nwork = nch == 1 ? nplanes : (nplanes + 7) / 8 * 8 * nch;
+    auto plane_of = [&](long w, int& cw) -> long {
+      if (nch == 1) {
+        cw = 0;
+        return w;
+      }
+      cw = (int)((w >> 3) % nch);
+      return (w / (8L * nch)) * 8 + (w & 7);
+    };
+    // item q (PERSIST) or this work-group's item -> (z, chain, state pointers);
+    // false for padding
+    auto locate = [&](long q, int& zq, int& cq, Ptrs& Pq) -> bool {
       long sq;
       if constexpr (PERSIST != 0) {
+        const long u = plane_of(q, cq);
+        if (u >= nplanes) return false;
         if (a.states_fast) {
-          sq = q % a.nstates + a.state0;
-          zq = (int)(q / a.nstates);
+          sq = u % a.nstates + a.state0;
+          zq = (int)(u / a.nstates);
         } else {
-          zq = (int)(q % a.nz);
-          sq = q / a.nz + a.state0;
+          zq = (int)(u % a.nz);
+          sq = u / a.nz + a.state0;
         }
       } else {
+        const long u = plane_of((long)blockIdx.x, cq);
         if (a.states_fast) {
+          if (u >= a.nstates) return false;
           zq = blockIdx.y;
-          sq = (long)blockIdx.x + a.state0;
+          sq = u + a.state0;
         } else {
-          zq = blockIdx.x;
+          if (u >= a.nz) return false;
+          zq = (int)u;
           sq = (long)blockIdx.y + a.state0;
         }
       }
       Pq = ptrs_of(sq);
+      return true;
     };
     constexpr int NPRE = MODE == PM_FWD ? XR * EX : EY;
     cx<F> pre[NPRE];
@@ -338,18 +361,31 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
         column_load(Pq.spec + (long)zq * plane_spec, pre);
       }
     };
-    int z;
+    const long pstep = PERSIST ? (long)gridDim.x : 0;
+    long p = PERSIST ? (long)blockIdx.x : 0;
+    int z, ch;
     Ptrs P;
-    locate(p, z, P);
+    // (a whole work-group leaves here together: no barrier has been reached)
+    if constexpr (PERSIST != 0) {
+      while (p < nwork && !locate(p, z, ch, P)) p += pstep;
+      if (p >= nwork) return;
+    } else {
+      if (!locate(0, z, ch, P)) return;
+    }
     prefetch(z, P);
     for (;;) {
-      const long pn = p + (PERSIST ? (long)gridDim.x : 0);
-      const bool more = PERSIST && pn < nplanes;
-      int zn = z;
+      long pn = p + pstep;
+      if constexpr (PERSIST != 0) {
+        int cn;
+        while (pn < nwork && plane_of(pn, cn) >= nplanes) pn += pstep;
+      }
+      const bool more = PERSIST && pn < nwork;
+      int zn = z, chn = ch;
       Ptrs Pn = P;
       const long z_real = (long)z * plane_real;
       if constexpr (MODE == PM_FWD) {
-        gp<const F> __restrict__ fac = (a.fac_index >= 0 && P.facz) ? P.facz + z_real : nullptr;
+        gp<const F> __restrict__ fac =
+            (a.fac_index >= 0 && P.facz) ? P.facz + (long)(2 * ch) * a.fac_table_stride + z_real : nullptr;
 #pragma unroll
         for (int rr = 0; rr < XR; ++rr) {
           const int row = rr * RPR + rloc;
@@ -374,13 +410,13 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
           }
         }
         if (more) {
-          locate(pn, zn, Pn);
+          locate(pn, zn, chn, Pn);
           prefetch(zn, Pn);
         }
       } else {
         column_inverse_regs(pre);
         if (more) {
-          locate(pn, zn, Pn);
+          locate(pn, zn, chn, Pn);
           prefetch(zn, Pn);
         }
         gp<const F> __restrict__ fac = P.facz + z_real;
@@ -411,11 +447,12 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
           }
         }
       }
-      column_forward_store(P.spec + (long)z * plane_spec);
+      column_forward_store(P.spec + (long)ch * P.chain_stride + (long)z * plane_spec);
       if (!more) break;
       __syncthreads();   // the DC / Nyquist epilogue still reads the plane in LDS
       p = pn;
       z = zn;
+      ch = chn;
       P = Pn;
     }
   } else if constexpr (MODE == PM_TAIL) {
@@ -812,15 +849,19 @@ hipError_t launch_rows(int is_double, int mode, int nx, const PlaneArgs& a, int 
 
 // ------------------------------------------------------------------ launchers
 template <typename F, int N>
-static hipError_t launch_plane_n(int mode, const PlaneArgs& a, int nz, int nstates, hipStream_t st) {
+static hipError_t launch_plane_n(int mode, const PlaneArgs& a0, int nz, int nstates, hipStream_t st) {
   dim3 block(PlaneShape<N>::BLOCK);
+  PlaneArgs a = a0;
+  a.nz = nz;
+  a.nstates = nstates;
+  if (mode != PM_FWD) a.fwd_chains = 0;
+  const int nch = a.fwd_chains > 1 ? a.fwd_chains : 1;
   if constexpr (N >= 64) {
     if (a.persist_blocks > 0 && (a.persist_mode == 1 || a.persist_mode == 2) && (mode == PM_FWD || mode == PM_LINK)) {
-      PlaneArgs b = a;
-      b.nz = nz;
-      b.nstates = nstates;
+      const PlaneArgs& b = a;
       const long nplanes = (long)nz * nstates;
-      dim3 grid((unsigned)(a.persist_blocks < nplanes ? a.persist_blocks : nplanes));
+      const long nwork = nch == 1 ? nplanes : (nplanes + 7) / 8 * 8 * nch;
+      dim3 grid((unsigned)(a.persist_blocks < nwork ? a.persist_blocks : nwork));
       if (a.persist_mode == 1) {
         if (mode == PM_FWD) hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD, 1>), grid, block, 0, st, b);
         else hipLaunchKernelGGL((plane_kernel<F, N, PM_LINK, 1>), grid, block, 0, st, b);
@@ -838,8 +879,11 @@ static hipError_t launch_plane_n(int mode, const PlaneArgs& a, int nz, int nstat
   // stream past
   dim3 grid(nz, nstates), grid_t(nstates, nz);
   const dim3 grid_fl = a.states_fast ? grid_t : grid;   // forward / link: either order
+  // forward launches forming several chains: nch items per plane, the fast
+  // extent padded to a multiple of 8 (see the item map in plane_kernel)
+  const dim3 grid_fwd = nch == 1 ? grid_fl : dim3((unsigned)((grid_fl.x + 7) / 8 * 8 * nch), grid_fl.y);
   switch (mode) {
-    case PM_FWD: hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD, 0>), grid_fl, block, 0, st, a); break;
+    case PM_FWD: hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD, 0>), grid_fwd, block, 0, st, a); break;
     case PM_LINK: hipLaunchKernelGGL((plane_kernel<F, N, PM_LINK, 0>), grid_fl, block, 0, st, a); break;
     case PM_TAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_TAIL, 0>), grid_t, block, 0, st, a); break;
     case PM_HTAIL: hipLaunchKernelGGL((plane_kernel<F, N, PM_HTAIL, 0>), grid_fl, block, 0, st, a); break;

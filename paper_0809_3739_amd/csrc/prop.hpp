@@ -39,13 +39,18 @@ struct PlaneArgs {
   const StateDesc* desc;      // optional per-state addresses (batched launches)
   long real_state_stride;     // elements between consecutive states (real arrays)
   long spec_state_stride;     // elements between consecutive states (spectra)
-  long chain_stride;          // PM_TAIL: elements between the chains' spectra
+  long chain_stride;          // PM_TAIL, PM_FWD: elements between the chains' spectra
   long fac_table_stride;      // elements between consecutive factor tables (= N)
   int fac_index;              // PM_FWD / PM_LINK: factor table used, -1 for none
   int chain;                  // desc mode: chain of this launch
   int state0;                 // first state of this launch
   int K;                      // PM_TAIL: number of chains
   double coef[MAX_K];         // PM_TAIL: c_1..c_K
+  // PM_FWD: chains formed from one read of the rows (0 or 1: one); chain c
+  // takes factor table fac_index + 2c and writes spec + c * chain_stride (the
+  // first potential half-steps exp(-dt V / 2k) of chains k = 1..K are tables
+  // 1, 3, .., 2K - 1)
+  int fwd_chains;
   // PM_FWD / PM_LINK launch shape (grids of 64 points and more): persist_mode
   // 0 = one work-group per (z, state) plane; 1 / 2 = persist_blocks resident
   // work-groups looping over the planes, each loading the next plane's input
@@ -58,7 +63,7 @@ struct PlaneArgs {
   // in flight share a few z planes, so each factor-table plane is fetched into
   // an XCD's L2 once and read there by every state)
   int states_fast;
-  int nz, nstates;            // set by the launcher for persistent launches
+  int nz, nstates;            // set by the launcher
   int ny;                     // row passes: rows per z plane
 };
 
