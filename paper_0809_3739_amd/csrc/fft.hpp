@@ -46,9 +46,74 @@ __device__ __forceinline__ cx<F> gload(gp<const cx<F>> p) {
   const vec2<F> t = *reinterpret_cast<gp<const vec2<F>>>(p);
   return cx<F>{t.x, t.y};
 }
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+// A vector-memory store of 16 bytes per lane reads its data registers after it
+// has issued.  Measured on MI355X: when the next two instruction slots write
+// one of those registers (the compiler reuses them at once), the store now and
+// then writes the new value into its first dword: a complex double comes out
+// with the low word of its real part replaced, at random lanes and planes.
+// Every such store is therefore followed by this two-slot pause that reads
+// the data registers, so that they stay unchanged until after it.
+__device__ __forceinline__ void hold_store_data(v4i32 t) { asm volatile("s_nop 1" ::"v"(t)); }
+
 template <typename F>
 __device__ __forceinline__ void gstore(gp<cx<F>> p, cx<F> v) {
   *reinterpret_cast<gp<vec2<F>>>(p) = vec2<F>{v.x, v.y};
+}
+template <>
+__device__ __forceinline__ void gstore<double>(gp<cx<double>> p, cx<double> v) {
+  const vec2<double> t = {v.x, v.y};
+  *reinterpret_cast<gp<vec2<double>>>(p) = t;
+  hold_store_data(__builtin_bit_cast(v4i32, t));
+}
+
+// Buffer (MUBUF) accesses of complex values: the wave-uniform part of an
+// address (the base of a plane, a constant offset) stays in scalar registers
+// and one 32-bit per-lane byte offset serves every access of a lane, so no
+// 64-bit address is formed per access.  The resource's byte range bounds the
+// accesses: beyond it loads read 0 and stores are dropped.  Word 3 of the
+// resource (0x00020000: 32-bit data format, the untyped-access setting of
+// gfx9-family parts) makes the loads valid.
+// The base must be the same in every lane (the resource lives in scalar
+// registers); it is passed through readfirstlane, which costs nothing where
+// the compiler already holds it in scalar registers and spares a per-access
+// loop over distinct resources where its analysis cannot see the uniformity
+// (values carried around the persistent plane loop).
+using brsrc = __amdgpu_buffer_rsrc_t;
+template <typename T>
+__device__ __forceinline__ brsrc make_brsrc(gp<T> base, unsigned bytes) {
+  const unsigned long long b = (unsigned long long)base;
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  void* u = (void*)(((unsigned long long)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(u, (short)0, (int)bytes, 0x00020000);
+}
+typedef int v2i32 __attribute__((ext_vector_type(2)));
+template <typename F>
+__device__ __forceinline__ cx<F> bload(brsrc r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ cx<float> bload<float>(brsrc r, unsigned voff, unsigned soff) {
+  const v2i32 t = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+  return cx<float>{__int_as_float(t.x), __int_as_float(t.y)};
+}
+template <>
+__device__ __forceinline__ cx<double> bload<double>(brsrc r, unsigned voff, unsigned soff) {
+  const v4i32 t = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+  return cx<double>{__hiloint2double(t.y, t.x), __hiloint2double(t.w, t.z)};
+}
+template <typename F>
+__device__ __forceinline__ void bstore(brsrc r, unsigned voff, unsigned soff, cx<F> v);
+template <>
+__device__ __forceinline__ void bstore<float>(brsrc r, unsigned voff, unsigned soff, cx<float> v) {
+  const v2i32 t = {__float_as_int(v.x), __float_as_int(v.y)};
+  __builtin_amdgcn_raw_buffer_store_b64(t, r, (int)voff, (int)soff, 0);
+}
+template <>
+__device__ __forceinline__ void bstore<double>(brsrc r, unsigned voff, unsigned soff, cx<double> v) {
+  const long long a = __double_as_longlong(v.x), b = __double_as_longlong(v.y);
+  const v4i32 t = {(int)(a & 0xffffffffLL), (int)(a >> 32), (int)(b & 0xffffffffLL), (int)(b >> 32)};
+  __builtin_amdgcn_raw_buffer_store_b128(t, r, (int)voff, (int)soff, 0);
+  hold_store_data(t);
 }
 
 template <typename F>

@@ -180,6 +180,16 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
     return tx == 0 ? LX - 1 : c - 1;
   };
   const int cs_col = cslot(col), cs_mirror = cslot(LX - col);
+  // Byte offsets of the buffer accesses (see bload): one per-lane offset per
+  // access pattern, the element's wave-uniform part in a compile-time offset.
+  // Real rows as complex pairs: row rr * RPR + rloc, pair tx + TX m.
+  constexpr unsigned CXB = sizeof(cx<F>);
+  constexpr unsigned REAL_PLANE_B = (unsigned)(NY * NX * sizeof(F)), SPEC_PLANE_B = (unsigned)(NY * NXH * CXB);
+  const unsigned row_vo = (unsigned)(rloc * LX + tx) * CXB;
+  auto row_so = [](int rr, int m) -> unsigned { return (unsigned)(rr * RPR * LX + TX * m) * CXB; };
+  // Spectrum columns: row tyc + TY m, column col (or LX, the Nyquist column).
+  const unsigned col_vo = (unsigned)(tyc * NXH + col) * CXB, nyq_vo = (unsigned)(tyc * NXH + LX) * CXB;
+  auto col_so = [](int m) -> unsigned { return (unsigned)(TY * m * NXH) * CXB; };
   auto cbuf = [&](int i) { return &lds[i * SROW + cs_col]; };
   // Row-transform exchange slots: element i of row r at r * SROW + i + i / EX.
   // The exchange writes lane t's outputs at E t + k; one pad slot per E
@@ -199,11 +209,11 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
   // the row's Nyquist value, which all lanes load too (one address per row), so
   // the loads stay full-wave instructions without a divergent branch.
   auto column_load = [&](gp<const cx<F>> __restrict__ spec, cx<F>* v) {
+    const brsrc r = make_brsrc(spec, SPEC_PLANE_B);
     if (cact) {
 #pragma unroll
       for (int m = 0; m < EY; ++m) {
-        const long o = (long)(tyc + TY * m) * NXH;
-        const cx<F> y0 = gload<F>(spec + o + col), yl = gload<F>(spec + o + LX);
+        const cx<F> y0 = bload<F>(r, col_vo, col_so(m)), yl = bload<F>(r, nyq_vo, col_so(m));
         v[m] = packed ? cx<F>{y0.x - yl.y, y0.y + yl.x} : y0;   // Y0 + i Y_LX
       }
     }
@@ -269,6 +279,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
       for (int m = 0; m < EY; ++m) lds[(tyc + TY * m) * SROW] = v[m];
     }
     __syncthreads();
+    const brsrc r = make_brsrc(spec, SPEC_PLANE_B);
     if (cact) {
 #pragma unroll
       for (int m = 0; m < EY; ++m) {
@@ -278,14 +289,14 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
         cx<F> o;
         o.x = packed ? hx : c.x;
         o.y = packed ? hy : c.y;
-        gstore<F>(spec + (long)ky * NXH + col, o);
+        bstore<F>(r, col_vo, col_so(m), o);
       }
       if (packed) {
 #pragma unroll
         for (int m = 0; m < EY; ++m) {
           const int ky = tyc + TY * m;
           const cx<F> c = v[m], cm = conj(lds[((NY - ky) % NY) * SROW]);
-          gstore<F>(spec + (long)ky * NXH + LX, muli<-1>(scale(c - cm, F(0.5))));
+          bstore<F>(r, nyq_vo, col_so(m), muli<-1>(scale(c - cm, F(0.5))));
         }
       }
     }
@@ -347,14 +358,13 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
     cx<F> pre[NPRE];
     auto prefetch = [&](int zq, const Ptrs& Pq) {
       if constexpr (MODE == PM_FWD) {
-        gp<const F> __restrict__ src = Pq.rin + (long)zq * plane_real;
+        const brsrc r = make_brsrc(Pq.rin + (long)zq * plane_real, REAL_PLANE_B);
 #pragma unroll
         for (int rr = 0; rr < XR; ++rr) {
           const int row = rr * RPR + rloc;
           if (row < NY) {
-            gp<const cx<F>> s2 = reinterpret_cast<gp<const cx<F>>>(src + (long)row * NX);
 #pragma unroll
-            for (int m = 0; m < EX; ++m) pre[rr * EX + m] = gload<F>(s2 + tx + TX * m);
+            for (int m = 0; m < EX; ++m) pre[rr * EX + m] = bload<F>(r, row_vo, row_so(rr, m));
           }
         }
       } else {
@@ -384,8 +394,9 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
       Ptrs Pn = P;
       const long z_real = (long)z * plane_real;
       if constexpr (MODE == PM_FWD) {
-        gp<const F> __restrict__ fac =
-            (a.fac_index >= 0 && P.facz) ? P.facz + (long)(2 * ch) * a.fac_table_stride + z_real : nullptr;
+        const bool has_fac = a.fac_index >= 0 && P.facz;
+        const brsrc rf = make_brsrc(has_fac ? P.facz + (long)(2 * ch) * a.fac_table_stride + z_real : P.facz,
+                                    REAL_PLANE_B);   // (not read without a factor table)
 #pragma unroll
         for (int rr = 0; rr < XR; ++rr) {
           const int row = rr * RPR + rloc;
@@ -394,11 +405,10 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
           cx<F> v[EX];
 #pragma unroll
           for (int m = 0; m < EX; ++m) v[m] = pre[rr * EX + m];
-          if (act && fac) {
-            gp<const cx<F>> f2 = reinterpret_cast<gp<const cx<F>>>(fac + (long)row * NX);
+          if (act && has_fac) {
 #pragma unroll
             for (int m = 0; m < EX; ++m) {
-              const cx<F> fv = gload<F>(f2 + tx + TX * m);
+              const cx<F> fv = bload<F>(rf, row_vo, row_so(rr, m));
               v[m].x *= fv.x;
               v[m].y *= fv.y;
             }
@@ -419,7 +429,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
           locate(pn, zn, chn, Pn);
           prefetch(zn, Pn);
         }
-        gp<const F> __restrict__ fac = P.facz + z_real;
+        const brsrc rf = make_brsrc(P.facz + z_real, REAL_PLANE_B);
 #pragma unroll
         for (int rr = 0; rr < XR; ++rr) {
           const int row = rr * RPR + rloc;
@@ -432,10 +442,9 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
           }
           fft<LX, +1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
           if (act) {
-            gp<const cx<F>> f2 = reinterpret_cast<gp<const cx<F>>>(fac + (long)row * NX);
 #pragma unroll
             for (int m = 0; m < EX; ++m) {
-              const cx<F> fv = gload<F>(f2 + tx + TX * m);
+              const cx<F> fv = bload<F>(rf, row_vo, row_so(rr, m));
               v[m].x *= fv.x;
               v[m].y *= fv.y;
             }
@@ -462,7 +471,6 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
     gp<cx<F>> spec = P.spec;
     gp<const F> facb = P.facb;
     const long chain_stride = P.chain_stride;
-    gp<const F> rin = P.rin;
     gp<F> rout = P.rout;
     double acc[XR][EX][2];
 #pragma unroll
@@ -475,7 +483,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
     cx<F> vc[EY];
     column_load(spec0, vc);
     for (int k = 0; k < a.K; ++k) {
-      gp<const F> __restrict__ fac = facb + (long)(2 * k + 1) * a.fac_table_stride + z_real;
+      const brsrc rf = make_brsrc(facb + (long)(2 * k + 1) * a.fac_table_stride + z_real, REAL_PLANE_B);
       const double ck = a.coef[k];
       column_inverse_regs(vc);
       // (float64 planes, and float32 planes with 24-element columns, have no
@@ -497,10 +505,9 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
         }
         fft<LX, +1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
         if (act) {
-          gp<const cx<F>> f2 = reinterpret_cast<gp<const cx<F>>>(fac + (long)row * NX);
 #pragma unroll
           for (int m = 0; m < EX; ++m) {
-            const cx<F> fv = gload<F>(f2 + tx + TX * m);
+            const cx<F> fv = bload<F>(rf, row_vo, row_so(rr, m));
             acc[rr][m][0] += ck * (double)(v[m].x * fv.x);
             acc[rr][m][1] += ck * (double)(v[m].y * fv.y);
           }
@@ -511,14 +518,14 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
         if (k + 1 < a.K) column_load(spec0 + (long)(k + 1) * chain_stride, vc);
       }
     }
-    gp<F> __restrict__ dst = rout + z_real;
+    const brsrc rd = make_brsrc(rout + z_real, REAL_PLANE_B);
 #pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
       if (row < NY) {
-        gp<cx<F>> d2 = reinterpret_cast<gp<cx<F>>>(dst + (long)row * NX);
 #pragma unroll
-        for (int m = 0; m < EX; ++m) gstore<F>(d2 + tx + TX * m, cx<F>{(F)acc[rr][m][0], (F)acc[rr][m][1]});
+        for (int m = 0; m < EX; ++m)
+          bstore<F>(rd, row_vo, row_so(rr, m), cx<F>{(F)acc[rr][m][0], (F)acc[rr][m][1]});
       }
     }
   } else {  // PM_HTAIL, PM_OUT
@@ -527,13 +534,12 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
     const long z_real = (long)z * plane_real, z_spec = (long)z * plane_spec;
     gp<cx<F>> spec = P.spec;
     gp<const F> facb = P.facb;
-    const long chain_stride = P.chain_stride;
     gp<const F> rin = P.rin;
     gp<F> rout = P.rout;
     column_inverse(spec + z_spec);
-    gp<const F> __restrict__ phi = rin + z_real;
-    gp<const F> __restrict__ V = (MODE == PM_OUT ? P.facz : facb) + z_real;
-    gp<F> __restrict__ dst = rout + z_real;
+    const brsrc rp = make_brsrc(MODE == PM_OUT ? rin : rin + z_real, REAL_PLANE_B);   // (PM_OUT: not read)
+    const brsrc rv = make_brsrc((MODE == PM_OUT ? P.facz : facb) + z_real, REAL_PLANE_B);
+    const brsrc rd = make_brsrc(rout + z_real, REAL_PLANE_B);
 #pragma unroll
     for (int rr = 0; rr < XR; ++rr) {
       const int row = rr * RPR + rloc;
@@ -546,20 +552,17 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
       }
       fft<LX, +1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
       if (act) {
-        gp<const cx<F>> p2 = reinterpret_cast<gp<const cx<F>>>(phi + (long)row * NX);
-        gp<const cx<F>> v2 = reinterpret_cast<gp<const cx<F>>>(V + (long)row * NX);
-        gp<cx<F>> d2 = reinterpret_cast<gp<cx<F>>>(dst + (long)row * NX);
         if constexpr (MODE == PM_OUT) {
 #pragma unroll
           for (int m = 0; m < EX; ++m) {
-            const cx<F> wv = gload<F>(v2 + tx + TX * m);
-            gstore<F>(d2 + tx + TX * m, cx<F>{v[m].x * wv.x, v[m].y * wv.y});
+            const cx<F> wv = bload<F>(rv, row_vo, row_so(rr, m));
+            bstore<F>(rd, row_vo, row_so(rr, m), cx<F>{v[m].x * wv.x, v[m].y * wv.y});
           }
         } else {
 #pragma unroll
           for (int m = 0; m < EX; ++m) {
-            const cx<F> pv = gload<F>(p2 + tx + TX * m), wv = gload<F>(v2 + tx + TX * m);
-            gstore<F>(d2 + tx + TX * m, cx<F>{v[m].x + wv.x * pv.x, v[m].y + wv.y * pv.y});
+            const cx<F> pv = bload<F>(rp, row_vo, row_so(rr, m)), wv = bload<F>(rv, row_vo, row_so(rr, m));
+            bstore<F>(rd, row_vo, row_so(rr, m), cx<F>{v[m].x + wv.x * pv.x, v[m].y + wv.y * pv.y});
           }
         }
       }
@@ -612,10 +615,15 @@ __global__ __launch_bounds__(THREADS) void pencil_kernel(PencilArgs a) {
   const cx<F>* rz = rz_s;
   const F* tz = tz_s;
 
+  // buffer accesses (see bload): element (t + T m, gcol) at byte offset
+  // (t M + gcol) |cx| per lane plus T m M |cx| in a scalar register
+  const brsrc rdat = make_brsrc((gp<cx<F>>)data, (unsigned)((long)NZ * a.M * (long)sizeof(cx<F>)));
+  const unsigned vo = (unsigned)(t * a.M + gc) * (unsigned)sizeof(cx<F>);
+  const unsigned so_m = (unsigned)(T * a.M) * (unsigned)sizeof(cx<F>);
   cx<F> v[E];
   if (act) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = data[(long)(t + T * m) * a.M + gcol];
+    for (int m = 0; m < E; ++m) v[m] = bload<F>(rdat, vo, so_m * m);
   }
   __syncthreads();   // staged tables visible
   auto buf = [&](int i) { return &lds[i * CP + col]; };
@@ -641,7 +649,7 @@ __global__ __launch_bounds__(THREADS) void pencil_kernel(PencilArgs a) {
   }
   if (act) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) data[(long)(t + T * m) * a.M + gcol] = v[m];
+    for (int m = 0; m < E; ++m) bstore<F>(rdat, vo, so_m * m, v[m]);
   }
 }
 

@@ -332,12 +332,18 @@ class SolveResult:
     propagations: int = 0     # state propagations performed (fewer than iterations * m with locking)
 
 
+def flat(hist: list, window: int, gain: float) -> bool:
+    """True when the last ``window`` values lowered the best earlier one by less
+    than the fraction ``gain`` (False while fewer than window + 1 values exist)."""
+    return len(hist) > window and min(hist[-window:]) > (1.0 - gain) * min(hist[:-window])
+
+
 def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, reduce: float = 0.5,
           n_check: int | None = None, margin: float = 0.01, max_iter_per_level: int = 2000,
           max_levels: int = 30, orthonormalize_first: bool = True, callback=None,
           stall_window: int | None = None, stall_gain: float = 0.02, accept=None,
           lock_tol: float | None = None, variance_every: int = 1, re_tol: float | None = None,
-          level_stall: int | None = None) -> SolveResult:
+          level_stall: int | None = None, stall_below: float | None = None) -> SolveResult:
     """Iterate with the protocol of Section III until R^H_j < gamma for the
     first ``n_check`` states.
 
@@ -373,6 +379,13 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
     only), above the variance bound, so the fixed point at this dt shows as R^H
     no longer falling; the R^H test then decides as after a variance-test exit.
     (With ``stall_window`` a stall ends the whole solve first.)
+
+    With ``stall_below`` both stall tests apply only once the level's best max
+    R^H is below ``stall_below``: a rounding floor lies a few gamma up, and far
+    above it a slow fall is slow convergence (a small gap at the edge of the
+    block), which a change of precision or dt would only make slower.  A level
+    whose best max R^H has not fallen by ``stall_gain`` over ten windows counts
+    as stalled at any height.
 
     With ``re_tol`` the fixed-dt test is max_j R^E_perp_j exp(2 dt theta_j)
     <= re_tol instead: R^E_perp relative to the propagated norm S_jj ~
@@ -434,13 +447,13 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
                     break
                 if it > 0 and rep <= ge and locked == 0:
                     break
-                if stall_window and it >= stall_window:
-                    before = min(rh_level[:-stall_window])
-                    if min(rh_level[-stall_window:]) > (1.0 - stall_gain) * before:
-                        return result(out["eig"], out["rh"], level + 1, False, stalled=True)
-                if level_stall and it >= level_stall and locked == 0:
-                    if min(rh_level[-level_stall:]) > (1.0 - stall_gain) * min(rh_level[:-level_stall]):
-                        break
+                near_floor = stall_below is None or min(rh_level) < stall_below
+                if stall_window and ((near_floor and flat(rh_level, stall_window, stall_gain))
+                                     or flat(rh_level, 10 * stall_window, stall_gain)):
+                    return result(out["eig"], out["rh"], level + 1, False, stalled=True)
+                if level_stall and locked == 0 and ((near_floor and flat(rh_level, level_stall, stall_gain))
+                                                    or flat(rh_level, 10 * level_stall, stall_gain)):
+                    break
                 confirm = False
                 if lock_tol is not None:
                     nl = 0
@@ -464,7 +477,7 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
 def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8,
                  stall_window: int = 20, check_below: float = 10.0, check_every: int = 10, callback=None,
                  lock32: float | None = None, lock64: float | None = None, variance_every32: int = 10,
-                 **kw) -> SolveResult:
+                 stall_below: float | None = None, **kw) -> SolveResult:
     """Float32 iterations until converged, then float64 only if needed.
 
     Float32 arithmetic puts a floor under the R^H it measures (the transforms'
@@ -481,6 +494,9 @@ def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0
     is propagated); ``variance_every32`` is the float32 stage's
     ``variance_every`` (10: that stage ends by R^H, the float64 check or a
     stall, so its variances are only needed for the rare level change).
+    ``stall_below`` (default 100 gamma) is the float32 stage's: its floor sits
+    at a few gamma, so a slow fall far above it is slow convergence and stays
+    in float32, three times cheaper per iteration than float64.
     """
     t0 = time.perf_counter()
     n_check = kw.get("n_check") or plan32.n_states
@@ -500,7 +516,8 @@ def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0
         return None
 
     r1 = solve(plan32, psi32, dt0=dt0, gamma=gamma, stall_window=stall_window, callback=callback, accept=accept,
-               lock_tol=lock32, variance_every=variance_every32, **kw)
+               lock_tol=lock32, variance_every=variance_every32,
+               stall_below=100.0 * gamma if stall_below is None else stall_below, **kw)
     stages = [{"precision": "fp32", "iterations": r1.iterations, "seconds": round(r1.seconds, 3), "dt": r1.dt,
                "float64_checks": box.get("checks", 0), "max_rh": float(np.max(r1.rh[:n_check]))}]
     if r1.converged:

@@ -98,6 +98,26 @@ def test_stall_ends_the_solve_without_convergence():
     assert r.iterations == 6
 
 
+def test_slow_fall_far_above_the_floor_is_not_a_stall():
+    """A max R^H falling 1 % per 20 iterations at 1e-4: without stall_below the
+    20-iteration window calls it a stall; with stall_below = 1e-6 the solve goes
+    on (the floor is far below), until the fall flattens near the floor."""
+    m = 2
+    slow = [([1e-4 * 0.9995 ** i] * m, [1.0] * m) for i in range(60)]
+    near = [([5e-7] * m, [1.0] * m)] * 30
+    r = solver.solve(ScriptedPlan(m, 2, slow + near), None, gamma=1e-10, stall_window=20)
+    assert r.stalled and r.iterations == 21
+    r = solver.solve(ScriptedPlan(m, 2, slow + near), None, gamma=1e-10, stall_window=20, stall_below=1e-6)
+    assert r.stalled and r.iterations == 60 + 21          # the plateau at 5e-7 is below 1e-6
+
+
+def test_flat_at_any_height_over_ten_windows_is_a_stall():
+    m = 2
+    script = [([1e-3, 1e-3], [1.0, 1.0])] * 80
+    r = solver.solve(ScriptedPlan(m, 2, script), None, gamma=1e-10, stall_window=5, stall_below=1e-6)
+    assert r.stalled and r.iterations == 51
+
+
 @pytest.mark.parametrize("lock", [None, 1e-11])
 def test_accept_hook_ends_the_solve(lock):
     m = 2

@@ -95,6 +95,31 @@ def test_step_matches_oracle(P, grid, box, m, order, prec, dt):
     assert err < tol
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plane_passes_are_reproducible(P, prec):
+    """Repeated steps and H applications of one block are bit-identical, and the
+    step matches the oracle.  (Float64 planes of 128 points once differed from
+    run to run at random lanes: a 16-byte store whose data registers the next
+    instruction overwrote wrote the new value into its first dword.)"""
+    grid, box = (128, 128, 8), (16.0, 16.0, 8.0)
+    say("reproducible passes", grid, prec)
+    V = toy_potential(grid, box)
+    psi0 = rounded(W.random_states(21, 2, grid), prec)
+    plan = P.Plan(grid, box, 2, 8, prec)
+    plan.set_potential(V)
+    steps, hs = [], []
+    for _ in range(6):
+        q = plan.new_states(psi0)
+        plan.step(q, 0.4)
+        steps.append(q.cpu().numpy())
+        hs.append(plan.apply_h(plan.new_states(psi0)).cpu().numpy())
+    assert all(np.array_equal(a, steps[0]) for a in steps[1:])
+    assert all(np.array_equal(a, hs[0]) for a in hs[1:])
+    err = rel_err(steps[0].astype(np.float64), oracle.mpe_apply(psi0, V, 0.4, 4, grid, box))
+    say("  rel err", err)
+    assert err < (STEP64 if prec == "fp64" else STEP32) * sum_abs_c(8)
+
+
 H_CASES = [((8, 8, 8), "fp64"), ((32, 32, 16), "fp64"), ((48, 48, 64), "fp64"), ((128, 128, 32), "fp64"),
            ((96, 96, 96), "fp32"), ((192, 192, 8), "fp32")]
 
