@@ -8,7 +8,13 @@ Tolerances (relative to the largest reference magnitude unless stated):
   1e-12 for H, overlaps, Cholesky and Rayleigh-Ritz.
 * float32 path: STEP32 * sum_k |c_k| per step, where STEP32 bounds the relative
   error of one float32 chain (3-D transform roundoff ~ eps32 * log2 N per T2
-  plus one rounding of every table entry); 2e-6 for H and the rotations.
+  plus one rounding of every table entry; measured on MI355X at most 3.3e-7
+  per unit of sum_k |c_k|, so STEP32 = 1e-6); 2e-6 for H and the rotations.
+  Per-call float32 linear algebra (measured errors against the float64 oracle
+  in brackets, bars about three times them): Rayleigh-Ritz Ritz values 2e-7
+  (6.0e-8); float32-MFMA overlaps: Ritz values 2e-7 (5.7e-8), orthonormality
+  4e-7 (1.3e-7); BF16 x 6: 2e-7 (5.6e-8), BF16 x 3: 1e-5 (3.0e-6); locked
+  iterations: Ritz values 4e-7 (1.2e-7), subspace 1.5e-6 (4.3e-7).
 """
 import math
 import sys
@@ -24,7 +30,7 @@ from oracle import dense
 pytestmark = pytest.mark.gpu
 
 STEP64 = 1e-12
-STEP32 = 4e-6
+STEP32 = 1e-6
 
 
 def say(*a):
@@ -186,7 +192,7 @@ def test_rayleigh_ritz_matches_oracle(P, prec, m, grid):
     eig = plan.rayleigh_ritz(psi)
     theta, Pr, HPr, _ = oracle.rayleigh_ritz(Psi0, oracle.h_apply(Psi0, V, grid, box))
     say("  eig err", np.max(np.abs(eig - theta)) / np.max(np.abs(theta)))
-    assert np.max(np.abs(eig - theta)) < (1e-11 if prec == "fp64" else 2e-5) * np.max(np.abs(theta))
+    assert np.max(np.abs(eig - theta)) < (1e-11 if prec == "fp64" else 2e-7) * np.max(np.abs(theta))
     got = psi.cpu().numpy().astype(np.float64)
     # vectors are unique up to sign where the Ritz values are separated
     gaps = np.diff(theta)
@@ -257,7 +263,7 @@ def test_float32_overlap_gemms(P, m, grid):
     g = psi.cpu().numpy().astype(np.float64).reshape(m, -1)
     ortho = np.max(np.abs(g @ g.T - np.eye(m)))
     say("  orthonormality after two passes", ortho)
-    assert ortho < 1e-5
+    assert ortho < 4e-7
     Psi0, _, _ = oracle.cholesky_orthonormalize(phi)
     Psi0 = rounded(Psi0, "fp32")
     psi = plan.new_states(Psi0)
@@ -265,7 +271,7 @@ def test_float32_overlap_gemms(P, m, grid):
     theta, _, _, _ = oracle.rayleigh_ritz(Psi0, oracle.h_apply(Psi0, V, grid, box))
     err = np.max(np.abs(eig - theta)) / np.max(np.abs(theta))
     say("  eig err", err)
-    assert err < 2e-5
+    assert err < 2e-7
     dup = plan.new_states(np.concatenate([Psi0[:m - 1], Psi0[:1]]))
     from paper_0809_3739_amd import MpeError
     with pytest.raises(MpeError):
@@ -275,7 +281,7 @@ def test_float32_overlap_gemms(P, m, grid):
         p64.set_gemm_precision("fp32")
 
 
-@pytest.mark.parametrize("mode,bar", [("bf16x6", 2e-6), ("bf16x3", 1e-4)])
+@pytest.mark.parametrize("mode,bar", [("bf16x6", 2e-7), ("bf16x3", 1e-5)])
 @pytest.mark.parametrize("m,grid", [(20, (32, 32, 32)), (125, (16, 16, 16))])
 def test_bf16_split_overlap_gemms(P, mode, bar, m, grid):
     """BF16-split overlap GEMMs (3 or 6 bf16 MFMA products per float32 product):
@@ -308,7 +314,7 @@ def test_bf16_split_overlap_gemms(P, mode, bar, m, grid):
     ortho = np.max(np.abs(g @ g.T - np.eye(m)))
     say(f"  eig err {err:.2e} orthonormality after two passes {ortho:.2e}")
     assert err < 10 * bar
-    assert ortho < max(10 * bar, 1e-5)
+    assert ortho < 4 * bar
     p64 = P.Plan(grid, box, m, 2, "fp64")
     from paper_0809_3739_amd import MpeError
     with pytest.raises(MpeError):
@@ -697,7 +703,7 @@ def test_locked_iterate_matches_oracle(P, grid, box, m, order, prec, locks):
     V = toy_potential(grid, box)
     psi0 = W.random_states(31, m, grid)
     ref0, _, _ = oracle.cholesky_orthonormalize(rounded(psi0, prec))
-    tol_e, tol_p = (1e-10, 1e-9) if prec == "fp64" else (2e-5, 2e-4)
+    tol_e, tol_p = (1e-10, 1e-9) if prec == "fp64" else (4e-7, 1.5e-6)
     for locked in locks:
         say("locked iterate", grid, prec, "m", m, "order", order, "locked", locked)
         plan = P.Plan(grid, box, m, order, prec)

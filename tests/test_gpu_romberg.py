@@ -4,9 +4,10 @@ oracle, through the C ABI (mpe_set_propagator on an order-4 plan).
 Bars: one Romberg step is three order-4 steps and a float64 combination with
 weights -1/15 and 16/15, so its rounding is that of three order-4 steps times
 17/15: float64 3 * 1e-12 * sum|c_k| (sum|c_k| = 5/3 for order 4); float32
-3 * 4e-6 * sum|c_k| (the intermediate T4(dt/2) block is stored in float32 once
-more).  Iterations: as the expansion's iterations (1e-10 / 1e-9 float64,
-1e-6 float32 Ritz values).
+3 * 1e-6 * sum|c_k| (the intermediate T4(dt/2) block is stored in float32 once
+more; measured 7.0e-7 against the bar 5e-6).  Iterations: as the expansion's
+iterations (1e-10 / 1e-9 float64, 1e-6 / 1.5e-6 float32 Ritz values /
+subspace; measured 1.1e-7 / 4.1e-7).
 """
 import math
 import sys
@@ -73,7 +74,7 @@ def test_romberg6_step_matches_oracle(P, grid, box, m, prec, dt):
     got = psi.cpu().numpy().astype(np.float64)
     ref = oracle.romberg6_apply(psi0, V, dt, grid, box)
     err = rel_err(got, ref)
-    tol = 3 * (1e-12 if prec == "fp64" else 4e-6) * SUM_C4
+    tol = 3 * (1e-12 if prec == "fp64" else 1e-6) * SUM_C4
     # the expansion's T4 of the same plan is a different operator
     off = rel_err(oracle.mpe_apply(psi0, V, dt, 2, grid, box), ref)
     say(f"  rel err {err:.2e} tol {tol:.1e}; T4 differs by {off:.2e}")
@@ -104,7 +105,7 @@ def test_romberg6_iterate_matches_oracle(P, prec, locked):
         assert e < 1e-10 and proj < 1e-9
         np.testing.assert_allclose(out["re_perp"][locked:], r.re_perp[locked:], rtol=1e-8, atol=1e-16)
     else:
-        assert e < 1e-6 and proj < 1e-4
+        assert e < 1e-6 and proj < 1.5e-6
 
 
 def test_romberg6_graph_replay_matches_eager(P):

@@ -4,8 +4,11 @@ float64 planes of 192 points, and the forced three-pass form of grids the
 two-pass form also runs.
 
 Bars as for the two-pass steps (the same transforms, one more rounding per
-pass): float64 1e-12 * sum|c_k|, float32 4e-6 * sum|c_k| per step; H 1e-12 /
-2e-6; iterations 1e-10 (Ritz values) and 1e-9 (subspace) in float64.
+pass): float64 1e-12 * sum|c_k|, float32 1e-6 * sum|c_k| per step (measured
+at most 2.3e-7 per unit of sum|c_k|); H 1e-12 / 5e-7 (measured 1.5e-7 in
+float32); iterations 1e-10 (Ritz values) and 1e-9 (subspace) in float64; the
+three-pass float32 iteration against the two-pass one 1e-6 / 1e-5 (measured
+2.6e-7 / 3.1e-6).
 """
 import math
 import sys
@@ -81,7 +84,7 @@ def test_three_pass_step_matches_oracle(P, grid, box, m, order, prec, force):
     got = psi.cpu().numpy().astype(np.float64)
     ref = oracle.mpe_apply(psi0, V, 0.3, order // 2, grid, box)
     err = rel_err(got, ref)
-    tol = (1e-12 if prec == "fp64" else 4e-6) * sum_abs_c(order)
+    tol = (1e-12 if prec == "fp64" else 1e-6) * sum_abs_c(order)
     say(f"  rel err {err:.2e} tol {tol:.1e}")
     assert err < tol
 
@@ -100,7 +103,7 @@ def test_three_pass_apply_h_matches_oracle(P, grid, prec):
     ref = oracle.h_apply(psi0, V, grid, box, hbar2_over_m=0.8)
     err = rel_err(h, ref)
     say("  rel err", err)
-    assert err < (1e-12 if prec == "fp64" else 2e-6)
+    assert err < (1e-12 if prec == "fp64" else 5e-7)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -123,7 +126,7 @@ def test_three_pass_agrees_with_two_pass(P, prec):
     proj = float(np.linalg.norm(R - (R @ G.T) @ G) / math.sqrt(5))
     say(f"  eig rel {e:.2e} subspace {proj:.2e}")
     assert e < (1e-13 if prec == "fp64" else 1e-6)
-    assert proj < (1e-11 if prec == "fp64" else 1e-4)
+    assert proj < (1e-11 if prec == "fp64" else 1e-5)
 
 
 @pytest.mark.parametrize("locked,spl", [(0, 0), (3, 2)])
