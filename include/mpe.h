@@ -232,6 +232,8 @@ mpe_status mpe_set_states_per_launch(mpe_plan p, int32_t states);
  *   persistence 2: the same loop at the register budget of persistence 0;
  *   order 0: z planes fastest; order 1: states fastest (the work-groups in
  *            flight share a few z planes of the potential-factor table).
+ * The forward launch forms the first half-step and transform of all K chains
+ * (one work item per chain and plane, the K chains of a plane on one XCD).
  * The H application's last pass and the single-chain output passes follow
  * the link pass's order.
  * Results are bitwise identical for every shape.  MPE_ERR_INVALID_ARGUMENT
