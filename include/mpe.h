@@ -232,13 +232,17 @@ mpe_status mpe_set_states_per_launch(mpe_plan p, int32_t states);
  *   persistence 2: the same loop at the register budget of persistence 0;
  *   order 0: z planes fastest; order 1: states fastest (the work-groups in
  *            flight share a few z planes of the potential-factor table).
- * The forward launch forms the first half-step and transform of all K chains
- * (one work item per chain and plane, the K chains of a plane on one XCD).
+ * The forward launch forms the first half-step and transform of all K chains;
+ * in modes 0..5 one work item per chain and plane, the K chains of a plane on
+ * one XCD.  Forward modes 6 and 7 (the chain loop, z planes / states fastest,
+ * blocks_per_cu ignored) give each work-group one plane and have it form the K
+ * chains one after the other, reading the plane's rows again from its own
+ * CU's caches (grids with nx >= 64; smaller grids run them as modes 0 and 3).
  * The H application's last pass and the single-chain output passes follow
  * the link pass's order.
  * Results are bitwise identical for every shape.  MPE_ERR_INVALID_ARGUMENT
- * for another class, a mode outside 0..5 or blocks_per_cu outside 1..16
- * (persistent modes). */
+ * for another class, a mode outside 0..7 (forward) or 0..5 (link), or
+ * blocks_per_cu outside 1..16 (persistent modes). */
 mpe_status mpe_set_plane_shape(mpe_plan p, int32_t kernel_class, int32_t mode, int32_t blocks_per_cu);
 
 /* Precision of the overlap GEMMs (S = Phi Phi^T, Hs, the variance overlaps):
@@ -271,10 +275,11 @@ int32_t mpe_get_pencil_shape(mpe_plan p);
 mpe_status mpe_get_plane_shape(mpe_plan p, int32_t* shape);
 
 /* Autotuner: times the candidate plane shapes (mode, blocks per CU) in
- * {(0,0), (1,1), (2,1), (2,2), (2,4)} and the same five with states fastest
- * (modes 3..5), then the pencil tiles 0..2 with the chosen plane shapes, on
- * `reps` steps of psi (read only; the steps write the plan's workspace) at dt,
- * and keeps the fastest shape per pass.  With cache_path (may be NULL), a line
+ * {(0,0), (1,1), (2,1), (2,2), (2,4)}, the same five with states fastest
+ * (modes 3..5) and, for the forward pass, the chain loop (modes 6, 7), then
+ * the pencil tiles 0..2 with the chosen plane shapes, on `reps` steps of psi
+ * (read only; the steps write the plan's workspace) at dt, and keeps the
+ * fastest shape per pass.  With cache_path (may be NULL), a line
  * "key|fwd_mode fwd_bpc link_mode link_bpc pencil_tile" keyed by device, CU
  * count, grid, precision, block size and order is looked up first (no timing
  * on a hit; a line without the pencil tile reads as tile 0) and appended after

@@ -313,6 +313,16 @@ hipError_t for_groups(mpe_plan p, Fn fn, int first = 0) {
   return hipSuccess;
 }
 
+// forward-pass shape: modes 0..5 as for the link pass (persist kind mode % 3,
+// states fastest for mode / 3); 6 / 7 = the chain loop with z / states fastest
+void set_fwd_shape(mpe_plan p, PlaneArgs& a) {
+  const int m = p->pmode[0];
+  a.fwd_loop = m >= 6;
+  a.persist_mode = m >= 6 ? 0 : m % 3;
+  a.states_fast = m >= 6 ? m - 6 : m / 3;
+  a.persist_blocks = p->pbpc[0] * p->n_cu;
+}
+
 PlaneArgs plane_base(mpe_plan p) {
   PlaneArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -371,9 +381,7 @@ mpe_status enqueue_step(mpe_plan p, const void* src, void* dst, int first = 0, c
              a.spec = chain_spec(p, 0);
              a.chain_stride = (long)p->m * p->spec;
              a.state0 = s0;
-             a.persist_mode = p->pmode[0] % 3;
-             a.states_fast = p->pmode[0] / 3;
-             a.persist_blocks = p->pbpc[0] * p->n_cu;
+             set_fwd_shape(p, a);
              return launch_plane(p->dbl, PM_FWD, p->nx, a, p->nz, cnt, p->st);
            }, first));
     toc(p, t);
@@ -1252,11 +1260,13 @@ mpe_status mpe_set_plane_shape(mpe_plan p, int32_t kernel_class, int32_t mode, i
   if (!p) return MPE_ERR_INVALID_ARGUMENT;
   const int c = kernel_class == MPE_KC_PLANE_FWD ? 0 : kernel_class == MPE_KC_PLANE_LINK ? 1 : -1;
   if (c < 0) return fail(p, MPE_ERR_INVALID_ARGUMENT, "kernel_class must be MPE_KC_PLANE_FWD or MPE_KC_PLANE_LINK");
-  if (mode < 0 || mode > 5) return fail(p, MPE_ERR_INVALID_ARGUMENT, "mode must lie in 0..5");
-  if (mode % 3 > 0 && (blocks_per_cu < 1 || blocks_per_cu > 16))
+  if (mode < 0 || mode > (c == 0 ? 7 : 5))
+    return fail(p, MPE_ERR_INVALID_ARGUMENT, c == 0 ? "forward mode must lie in 0..7" : "link mode must lie in 0..5");
+  const bool persistent = mode < 6 && mode % 3 > 0;
+  if (persistent && (blocks_per_cu < 1 || blocks_per_cu > 16))
     return fail(p, MPE_ERR_INVALID_ARGUMENT, "blocks_per_cu must be in [1, 16] for a persistent shape");
   p->pmode[c] = mode;
-  p->pbpc[c] = mode % 3 > 0 ? blocks_per_cu : 0;
+  p->pbpc[c] = persistent ? blocks_per_cu : 0;
   p->shape_ver++;
   return MPE_OK;
 }
@@ -1344,8 +1354,9 @@ mpe_status mpe_autotune(mpe_plan p, const void* psi, double dt, int32_t reps, co
   }
   mpe_status s = ensure_tables(p, dt);
   if (s != MPE_OK) return s;
-  // candidate shapes (mode, work-groups per CU), timed on steps psi -> phi
-  const int cand[][2] = {{0, 0}, {1, 1}, {2, 1}, {2, 2}, {2, 4}, {3, 0}, {4, 1}, {5, 1}, {5, 2}, {5, 4}};
+  // candidate shapes (mode, work-groups per CU), timed on steps psi -> phi;
+  // the forward pass's chain loop (modes 6, 7) is timed beside link modes 0, 3
+  const int cand[][2] = {{0, 0}, {1, 1}, {2, 1}, {2, 2}, {2, 4}, {3, 0}, {4, 1}, {5, 1}, {5, 2}, {5, 4}, {6, 0}, {7, 0}};
   const int nc = (int)(sizeof cand / sizeof cand[0]);
   double best_ms[2] = {1e300, 1e300};
   int best_c[2] = {0, 0};
@@ -1356,7 +1367,9 @@ mpe_status mpe_autotune(mpe_plan p, const void* psi, double dt, int32_t reps, co
   for (int i = 0; i < MPE_KC_COUNT; ++i) saved_ms[i] = p->kms[i], saved_n[i] = p->kcount[i];
   p->prof = true;
   for (int c = 0; c < nc; ++c) {
-    p->pmode[0] = p->pmode[1] = cand[c][0];
+    const bool loop = cand[c][0] >= 6;
+    p->pmode[0] = cand[c][0];
+    p->pmode[1] = loop ? 3 * (cand[c][0] - 6) : cand[c][0];
     p->pbpc[0] = p->pbpc[1] = cand[c][1];
     s = enqueue_step(p, psi, p->phi);   // warm-up
     if (s != MPE_OK) break;
@@ -1366,7 +1379,7 @@ mpe_status mpe_autotune(mpe_plan p, const void* psi, double dt, int32_t reps, co
     if (s != MPE_OK) break;
     collect_times(p);
     const double t[2] = {p->kms[MPE_KC_PLANE_FWD], p->kms[MPE_KC_PLANE_LINK]};
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < (loop ? 1 : 2); ++k)
       if (t[k] < best_ms[k]) best_ms[k] = t[k], best_c[k] = c;
   }
   for (int i = 0; i < MPE_KC_COUNT; ++i) p->kms[i] = saved_ms[i], p->kcount[i] = saved_n[i];

@@ -70,7 +70,9 @@ struct PlaneOcc {
 };
 
 // PERSIST: 0 = one plane per work-group; 1 = persistent, register budget of one
-// work-group per CU; 2 = persistent at the occupancy of PERSIST = 0.
+// work-group per CU; 2 = persistent at the occupancy of PERSIST = 0; 3 (forward
+// pass forming several chains) = one plane per work-group, every chain of it in
+// turn, at the occupancy of PERSIST = 0.
 template <typename F, int NX, int MODE, int PERSIST>
 struct PlaneWaves {
   static constexpr int one_wg = (PlaneShape<NX>::BLOCK / 64 + 3) / 4;
@@ -96,6 +98,7 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
   static_assert(NCF * TY <= BLOCK, "one column round");
   static_assert(NCF % 2 == 0, "column pairs");
   static_assert(PERSIST == 0 || MODE == PM_FWD || MODE == PM_LINK, "persistent launches: forward and link passes");
+  static_assert(PERSIST != 3 || MODE == PM_FWD, "the chain loop is a forward-pass form");
   constexpr bool TAIL_PREFETCH = sizeof(F) == 4 && EY <= 16;
 
   __shared__ cx<F> lds[NY * SROW];
@@ -303,8 +306,8 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
   };
 
   if constexpr (MODE == PM_FWD || MODE == PM_LINK) {
-    // Work items of this work-group: one (chain, z, state) item, or with
-    // PERSIST every gridDim.x-th item of the launch; the next item's input
+    // Work items of this work-group: one (chain, z, state) item, or in a
+    // persistent launch every gridDim.x-th item of the launch; the next item's input
     // (rows for the forward pass, spectrum columns for the link pass) is
     // loaded while the current plane is transformed.
     // A forward launch can form several chains (fwd_chains) from each plane of
@@ -314,7 +317,11 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
     // index 8 (w / 8 nch) + w mod 8, plane indices padded to a multiple of 8
     // (the padding is skipped).  With one chain the item is the plane index.
     // The plane index runs over the (z, state) pairs with z or states fastest.
-    const int nch = (MODE == PM_FWD && a.fwd_chains > 1) ? a.fwd_chains : 1;
+    // In the chain loop (PERSIST = 3) a work-group forms every chain of its
+    // plane instead, one after the other, reading the rows again from its own
+    // CU's caches for each chain.
+    constexpr bool PERS = PERSIST == 1 || PERSIST == 2, CHAIN_LOOP = PERSIST == 3;
+    const int nch = (MODE == PM_FWD && a.fwd_chains > 1 && !CHAIN_LOOP) ? a.fwd_chains : 1;
     const long nplanes = (long)a.nz * a.nstates;
     const long nwork = nch == 1 ? nplanes : (nplanes + 7) / 8 * 8 * nch;
     auto plane_of = [&](long w, int& cw) -> long {
@@ -325,11 +332,11 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
       cw = (int)((w >> 3) % nch);
       return (w / (8L * nch)) * 8 + (w & 7);
     };
-    // item q (PERSIST) or this work-group's item -> (z, chain, state pointers);
-    // false for padding
+    // item q (persistent) or this work-group's item -> (z, chain, state
+    // pointers); false for padding
     auto locate = [&](long q, int& zq, int& cq, Ptrs& Pq) -> bool {
       long sq;
-      if constexpr (PERSIST != 0) {
+      if constexpr (PERS) {
         const long u = plane_of(q, cq);
         if (u >= nplanes) return false;
         if (a.states_fast) {
@@ -371,12 +378,12 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
         column_load(Pq.spec + (long)zq * plane_spec, pre);
       }
     };
-    const long pstep = PERSIST ? (long)gridDim.x : 0;
-    long p = PERSIST ? (long)blockIdx.x : 0;
+    const long pstep = PERS ? (long)gridDim.x : 0;
+    long p = PERS ? (long)blockIdx.x : 0;
     int z, ch;
     Ptrs P;
     // (a whole work-group leaves here together: no barrier has been reached)
-    if constexpr (PERSIST != 0) {
+    if constexpr (PERS) {
       while (p < nwork && !locate(p, z, ch, P)) p += pstep;
       if (p >= nwork) return;
     } else {
@@ -385,11 +392,11 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
     prefetch(z, P);
     for (;;) {
       long pn = p + pstep;
-      if constexpr (PERSIST != 0) {
+      if constexpr (PERS) {
         int cn;
         while (pn < nwork && plane_of(pn, cn) >= nplanes) pn += pstep;
       }
-      const bool more = PERSIST && pn < nwork;
+      const bool more = PERS && pn < nwork;
       int zn = z, chn = ch;
       Ptrs Pn = P;
       const long z_real = (long)z * plane_real;
@@ -457,6 +464,40 @@ __attribute__((amdgpu_waves_per_eu(PlaneWaves<F, NX, MODE, PERSIST>::value))) vo
         }
       }
       column_forward_store(P.spec + (long)ch * P.chain_stride + (long)z * plane_spec);
+      if constexpr (CHAIN_LOOP) {
+        // the other chains of this plane: the rows again (from this CU's
+        // caches), each chain's factor table, the transforms, its own spectrum
+        // (a copy of the row pass above, with the rows loaded in place: kept in
+        // the loop, the prefetched rows' registers spill)
+        for (int c2 = 1; c2 < a.fwd_chains; ++c2) {
+          __syncthreads();   // the DC / Nyquist epilogue still reads the plane in LDS
+          const brsrc rsrc = make_brsrc(P.rin + z_real, REAL_PLANE_B);
+          const brsrc rf = make_brsrc(P.facz + (long)(2 * c2) * a.fac_table_stride + z_real, REAL_PLANE_B);
+#pragma unroll
+          for (int rr = 0; rr < XR; ++rr) {
+            const int row = rr * RPR + rloc;
+            const bool act = ALL_ROWS || row < NY;
+            const int rowc = act ? row : 0;
+            cx<F> v[EX];
+#pragma unroll
+            for (int m = 0; m < EX; ++m) v[m] = bload<F>(rsrc, row_vo, row_so(rr, m));
+            if (act) {
+#pragma unroll
+              for (int m = 0; m < EX; ++m) {
+                const cx<F> fv = bload<F>(rf, row_vo, row_so(rr, m));
+                v[m].x *= fv.x;
+                v[m].y *= fv.y;
+              }
+            }
+            fft<LX, -1, ROWWAVE>(v, tx, act, rowbuf(rowc), rx);
+            if (act) {
+#pragma unroll
+              for (int m = 0; m < EX; ++m) lds[row * SROW + rslot(m)] = v[m];
+            }
+          }
+          column_forward_store(P.spec + (long)c2 * P.chain_stride + (long)z * plane_spec);
+        }
+      }
       if (!more) break;
       __syncthreads();   // the DC / Nyquist epilogue still reads the plane in LDS
       p = pn;
@@ -887,6 +928,13 @@ static hipError_t launch_plane_n(int mode, const PlaneArgs& a0, int nz, int nsta
   // stream past
   dim3 grid(nz, nstates), grid_t(nstates, nz);
   const dim3 grid_fl = a.states_fast ? grid_t : grid;   // forward / link: either order
+  if constexpr (N >= 64) {
+    if (mode == PM_FWD && nch > 1 && a.fwd_loop) {
+      // chain loop: one work-group per plane forms all nch chains
+      hipLaunchKernelGGL((plane_kernel<F, N, PM_FWD, 3>), grid_fl, block, 0, st, a);
+      return hipGetLastError();
+    }
+  }
   // forward launches forming several chains: nch items per plane, the fast
   // extent padded to a multiple of 8 (see the item map in plane_kernel)
   const dim3 grid_fwd = nch == 1 ? grid_fl : dim3((unsigned)((grid_fl.x + 7) / 8 * 8 * nch), grid_fl.y);

@@ -51,6 +51,12 @@ struct PlaneArgs {
   // first potential half-steps exp(-dt V / 2k) of chains k = 1..K are tables
   // 1, 3, .., 2K - 1)
   int fwd_chains;
+  // PM_FWD with fwd_chains > 1, one work-group per plane (persist_mode 0):
+  // 0 = one work item per (chain, plane), the chains of a plane on one XCD;
+  // 1 = each work-group forms every chain of its plane in turn, reading the
+  //     rows again from its own CU's caches for chains after the first (grids
+  //     of 64 points and more; smaller grids take 0).  Both give the same bits.
+  int fwd_loop;
   // PM_FWD / PM_LINK launch shape (grids of 64 points and more): persist_mode
   // 0 = one work-group per (z, state) plane; 1 / 2 = persist_blocks resident
   // work-groups looping over the planes, each loading the next plane's input

@@ -932,6 +932,7 @@ def test_batch_iteration_matches_oracle(P):
 
 # ------------------------------------------------------------------ plane-pass launch shapes
 SHAPES = [(0, 0), (1, 1), (2, 1), (2, 2), (2, 3), (3, 0), (4, 1), (5, 2)]
+FWD_LOOP = [(6, 0), (7, 0)]   # forward pass only: the chain loop
 
 
 @pytest.mark.parametrize("prec,grid,ns,order", [("fp32", 64, 13, 8), ("fp64", 64, 7, 12), ("fp32", 96, 5, 6),
@@ -952,6 +953,13 @@ def test_plane_shapes_are_bitwise_identical(P, prec, grid, ns, order):
         outs.append(x.cpu())
     for sh, o in zip(SHAPES[1:], outs[1:]):
         assert torch.equal(o, outs[0]), sh
+    for shape in FWD_LOOP:
+        plan.set_plane_shape("plane_fwd", *shape)
+        for link in [(0, 0), (4, 1)]:
+            plan.set_plane_shape("plane_link", *link)
+            x = psi0.clone()
+            plan.step(x, 0.3)
+            assert torch.equal(x.cpu(), outs[0]), ("chain loop", shape, link)
     plan.set_plane_shape("plane_fwd", 0, 0)
     plan.set_plane_shape("plane_link", 0, 0)
     for tile in (1, 2, 0):
@@ -961,9 +969,9 @@ def test_plane_shapes_are_bitwise_identical(P, prec, grid, ns, order):
         assert torch.equal(x.cpu(), outs[0]), ("pencil tile", tile)
     # the fused iteration (graph replay) after shape changes
     eigs = []
-    for shape in [(0, 0), (1, 1), (2, 2), (3, 0), (5, 1)]:
+    for shape in [(0, 0), (1, 1), (2, 2), (3, 0), (5, 1), (7, 0)]:
         plan.set_plane_shape("plane_fwd", *shape)
-        plan.set_plane_shape("plane_link", *shape)
+        plan.set_plane_shape("plane_link", *shape if shape[0] < 6 else (3, 0))
         x = psi0.clone()
         plan.orthonormalize(x)
         eigs.append(plan.iterate(x, 0.3)["eig"])
@@ -998,7 +1006,11 @@ def test_autotune_and_cache(P, tmp_path):
     assert r2["plane_fwd"] == r["plane_fwd"] and r2["plane_link"] == r["plane_link"]
     from paper_0809_3739_amd import MpeError
     with pytest.raises(MpeError):
-        plan.set_plane_shape("plane_fwd", 6, 1)
+        plan.set_plane_shape("plane_fwd", 8, 0)
+    with pytest.raises(MpeError):
+        plan.set_plane_shape("plane_link", 6, 0)
+    with pytest.raises(MpeError):
+        plan.set_plane_shape("plane_fwd", 2, 17)
     with pytest.raises(MpeError):
         plan.set_plane_shape("pencil", 1, 1)
     with pytest.raises(MpeError):
