@@ -171,7 +171,7 @@ def start_quality(plan: solver.Plan, psi: torch.Tensor) -> dict:
 
 def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, order: int = 12,
                    gamma: float = 1e-8, variants=("learned_ladder_lock3_g32", "random_ladder_lock3_g32",
-                                                  "random_fp64_lock", "random_fp64"), log=print):
+                                                  "random_fp64_lock", "random_fp64"), log=print, dt0: float = 0.5):
     """Iterations and seconds to max_{j<120} R^H_j < gamma from the learned and the random start.
 
     ``*_ladder``: float32 iterations until gamma or the float32 floor, then
@@ -181,7 +181,7 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
     below ``f * gamma`` (f = 1 when omitted) in float32 and below ``gamma / 10``
     in float64.  ``_g32`` runs the float32 stage's overlaps on float32 MFMA, and
     a final ``_v<k>`` forms the float32 stage's variances only every k-th
-    iteration (10 when omitted).
+    iteration (10 when omitted).  Every variant starts at the step ``dt0``.
     """
     box = (BOX,) * 3
     p32 = solver.Plan((grid,) * 3, box, N_STATES, order, "fp32", n_guard=n_guard)
@@ -219,10 +219,11 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
             if base.endswith("fp64"):
                 psi = psi.to(torch.float64)
                 q = start_quality(p64, psi)
-                r = solver.solve(p64, psi, gamma=gamma, n_check=N_STATES, callback=progress, lock_tol=lock64)
+                r = solver.solve(p64, psi, dt0=dt0, gamma=gamma, n_check=N_STATES, callback=progress,
+                                 lock_tol=lock64)
             else:
                 q = start_quality(p32, psi)
-                r = solver.solve_ladder(p32, p64, psi, gamma=gamma, n_check=N_STATES, callback=progress,
+                r = solver.solve_ladder(p32, p64, psi, dt0=dt0, gamma=gamma, n_check=N_STATES, callback=progress,
                                         lock32=lock32, lock64=lock64, variance_every32=ve)
             torch.cuda.synchronize()
             secs = time.perf_counter() - t0
@@ -280,6 +281,7 @@ def main(argv=None):
     ap.add_argument("--eval-grid", type=int, default=128)
     ap.add_argument("--guards", type=int, default=5)
     ap.add_argument("--eval-gamma", type=float, default=1e-8)
+    ap.add_argument("--eval-dt0", type=float, default=0.5, help="initial step of every evaluated solve")
     ap.add_argument("--variants", default="learned_ladder_lock3_g32,random_ladder_lock3_g32,random_fp64_lock,random_fp64")
     a = ap.parse_args(argv)
 
@@ -293,7 +295,8 @@ def main(argv=None):
         meta = load_weights(net, a.out)
         log(f"[eval] weights {a.out}: {meta}")
         rows = compare_starts(net, [int(x) for x in a.eval_seeds.split(",")], grid=a.eval_grid,
-                              n_guard=a.guards, gamma=a.eval_gamma, variants=tuple(a.variants.split(",")), log=log)
+                              n_guard=a.guards, gamma=a.eval_gamma, variants=tuple(a.variants.split(",")), log=log,
+                              dt0=a.eval_dt0)
         if a.log:
             with open(a.log, "w") as f:
                 json.dump({"weights": meta, "rows": rows}, f, indent=1)
