@@ -359,9 +359,9 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
     plan's precision has been reached (in float32 it lies above the gamma
     that float64 reaches, and it rises as dt shrinks, so halving would not help).
 
-    ``accept(out, iteration)``, if given, is called after every iteration; a
-    non-None return {"eig", "rh"} ends the solve as converged with those values
-    (an external, more accurate convergence check).
+    ``accept(out, iteration, final=False)``, if given, is called after every
+    iteration; a non-None return {"eig", "rh"} ends the solve as converged with
+    those values (an external, more accurate convergence check).
 
     With ``lock_tol`` the solve propagates selectively (Section III: only
     states whose variance is still above the bound need propagating): after
@@ -370,7 +370,11 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
     iteration (``Plan.set_locked``).  R^H is evaluated for every state in every
     iteration, so a locked state whose R^H rises again is released at once;
     locks are dropped when dt changes, and a level only ends on an iteration
-    without locks, so its R^E test sees every state propagated.
+    without locks, so its R^E test sees every state propagated.  When every
+    one of the first ``n_check`` states is locked while max R^H is still above
+    gamma (``lock_tol`` >= gamma, as in a float32 stage that hands its states
+    to float64), nothing is left to propagate: ``accept`` is called once more
+    with ``final=True`` and, if it declines, the solve ends as stalled.
 
     A level also ends when max R^H has not improved by the fraction
     ``stall_gain`` over the last ``level_stall`` iterations (default 20 for
@@ -460,6 +464,15 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
                     rh = out["rh"]
                     while nl < n_check and rh[nl] <= lock_tol:
                         nl += 1
+                    if nl >= n_check:
+                        # every checked state is locked, yet max R^H >= gamma (so lock_tol >= gamma):
+                        # with nothing left to propagate among them, further iterations at this
+                        # precision cannot lower it; a last external check, else the solve stalls
+                        if accept is not None:
+                            ok = accept(out, total, True)
+                            if ok is not None:
+                                return result(ok["eig"], ok["rh"], level + 1, True)
+                        return result(out["eig"], out["rh"], level + 1, False, stalled=True)
                     if it > 0 and rep <= ge:
                         nl = 0   # the level may be done: confirm with every state propagated
                         confirm = True
@@ -486,8 +499,9 @@ def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0
     ``check_below * gamma``, every ``check_every`` iterations the block is
     converted to float64 and orthonormalised, Rayleigh-Ritz rotated and
     measured with the float64 plan; the solve ends there when that R^H is below
-    gamma.  If float32 stalls first, float64 iterations continue from the
-    converted states at the same dt until gamma.  The two plans must describe
+    gamma; once every checked state is locked in float32 (``lock32`` >= gamma)
+    one such check decides at once.  If float32 stalls first, float64
+    iterations continue from the converted states at the same dt until gamma.  The two plans must describe
     the same system; iterations and seconds of both stages are summed, and the
     result's ``psi`` is the float64 block.  ``lock32`` and ``lock64`` are the
     ``lock_tol`` of the two stages (selective propagation; None: every state
@@ -502,9 +516,12 @@ def solve_ladder(plan32: Plan, plan64: Plan, psi32: torch.Tensor, dt0: float = 0
     n_check = kw.get("n_check") or plan32.n_states
     box = {}
 
-    def accept(out, it):
-        if it % check_every or float(np.max(out["rh"][:n_check])) >= check_below * gamma:
+    def accept(out, it, final=False):
+        if final and box.get("checked_at") == it:
+            return None   # this iteration's block was checked already
+        if not final and (it % check_every or float(np.max(out["rh"][:n_check])) >= check_below * gamma):
             return None
+        box["checked_at"] = it
         psi64 = psi32.to(torch.float64)
         plan64.orthonormalize(psi64)
         eig = plan64.rayleigh_ritz(psi64)

@@ -212,3 +212,29 @@ def test_float32_level_ends_when_rh_stops_falling():
     plan64 = ScriptedPlan(m, 2, [([1e-6, 1e-6], [1e-7, 1e-7])] * 30 + [([1e-20] * m, [1e-7] * m)])
     r64 = solver.solve(plan64, None, dt0=0.4, gamma=1e-10, max_iter_per_level=30)
     assert plan64.dts == [0.4] * 30 + [0.2]       # float64: no stall exit, the level runs to its cap
+
+
+@pytest.mark.parametrize("passes", [False, True])
+def test_every_checked_state_locked_above_gamma_ends_the_stage(passes):
+    """lock_tol above gamma (a float32 stage): once the first n_check states are
+    all locked while max R^H is still above gamma, the next iterations would
+    propagate none of them; the solve asks accept once more (final=True) and
+    ends there, converged if it accepts, else stalled."""
+    m = 3
+    script = [
+        ([2e-10, 5e-4, 1e-3], [1.0] * m),      # one leading state below lock_tol
+        ([2e-10, 2.5e-10, 1e-3], [1.0] * m),   # both checked states locked, max R^H 2.5e-10 > gamma
+    ] + [([2e-10, 2.5e-10, 1e-3], [1.0] * m)] * 30
+    calls = []
+
+    def accept(out, it, final=False):
+        calls.append((it, final))
+        return {"eig": out["eig"], "rh": np.zeros(m)} if (final and passes) else None
+
+    plan = ScriptedPlan(m, 2, script)
+    r = solver.solve(plan, None, gamma=1e-10, lock_tol=3e-10, n_check=2, stall_window=20, accept=accept)
+    assert r.iterations == 2
+    assert calls == [(1, False), (2, False), (2, True)]
+    assert plan.locked_seen == [0, 1]
+    assert (r.converged, r.stalled) == ((True, False) if passes else (False, True))
+    assert plan.locked == 0
