@@ -241,16 +241,22 @@ def iterate(psi: np.ndarray, V: np.ndarray, dt: float, K: int, grid, box,
     Rayleigh-Ritz, and the variances R^E and R^H (Section III).
 
     ``locked``: selective propagation (Section III, only states whose variance is
-    still above the bound are propagated): the first ``locked`` states are taken
-    over unpropagated, phi_j = psi_j, before the orthonormalisation.
+    still above the bound are propagated): the locked states are taken over
+    unpropagated, phi_j = psi_j, before the orthonormalisation.  An integer
+    locks the first ``locked`` states, a sequence of indices locks those states.
     ``romberg6``: propagate with the Romberg-type T6 of Eq. sixp instead of the
     order-2K expansion (K is then ignored)."""
     phi = np.array(psi, dtype=np.float64, copy=True)
-    if locked < len(psi):
+    act = np.ones(len(psi), dtype=bool)
+    if np.ndim(locked) == 0:
+        act[:int(locked)] = False
+    else:
+        act[np.asarray(locked, dtype=np.int64)] = False
+    if act.any():
         if romberg6:
-            phi[locked:] = romberg6_apply(psi[locked:], V, dt, grid, box, hbar2_over_m)
+            phi[act] = romberg6_apply(psi[act], V, dt, grid, box, hbar2_over_m)
         else:
-            phi[locked:] = mpe_apply(psi[locked:], V, dt, K, grid, box, hbar2_over_m)
+            phi[act] = mpe_apply(psi[act], V, dt, K, grid, box, hbar2_over_m)
     re, re_perp, _ = residual_e(psi, phi)
     Psi, _, _ = cholesky_orthonormalize(phi)
     HPsi = h_apply(Psi, V, grid, box, hbar2_over_m)

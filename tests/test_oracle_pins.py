@@ -229,13 +229,14 @@ def test_residual_e_zero_on_exact_eigenvectors():
     assert rh.max() < 1e-24
 
 
-@pytest.mark.parametrize("locked", [0, 2, 5])
+@pytest.mark.parametrize("locked", [0, 2, 5, (1, 3), (0, 2, 4)])
 def test_locked_iteration_matches_dense_subspace(locked):
-    """Selective propagation (Section III): with the first ``locked`` states left
-    unpropagated, the iteration's Ritz pairs are those of H on
-    span{psi_0 .. psi_(locked-1), T psi_locked .. T psi_(m-1)}, built here from the
-    dense propagator matrix and a QR factorisation; R^E vanishes for the locked
-    states and equals the unlocked iteration's value for the others."""
+    """Selective propagation (Section III): with the locked states left
+    unpropagated, the iteration's Ritz pairs are those of H on the span of the
+    locked psi_j and of T psi_j for the others, built here from the dense
+    propagator matrix and a QR factorisation; R^E vanishes for the locked
+    states and equals the unlocked iteration's value for the others.  An
+    integer locks a leading run, a tuple any set of states."""
     grid, box = (8, 8, 8), (8.0, 8.0, 8.0)
     V = toy8(grid, box)
     m, K, dt = 5, 2, 0.3
@@ -243,8 +244,13 @@ def test_locked_iteration_matches_dense_subspace(locked):
     psi = Q0.T.reshape(m, *grid)
     H = dense.hamiltonian_dense(V, grid, box)
     M = dense.mpe_dense(V, grid, box, dt, K)
+    lk = np.zeros(m, dtype=bool)
+    if isinstance(locked, int):
+        lk[:locked] = True
+    else:
+        lk[list(locked)] = True
     B = Q0.copy()
-    B[:, locked:] = M @ Q0[:, locked:]
+    B[:, ~lk] = M @ Q0[:, ~lk]
     Qb, _ = np.linalg.qr(B)
     want = np.linalg.eigvalsh(Qb.T @ H @ Qb)
     r = mpe.iterate(psi, V, dt, K, grid, box, locked=locked)
@@ -253,9 +259,16 @@ def test_locked_iteration_matches_dense_subspace(locked):
     P = r.psi.reshape(m, -1).T
     assert np.abs(P @ (P.T @ Qb) - Qb).max() < 1e-10
     full = mpe.iterate(psi, V, dt, K, grid, box)
-    assert np.abs(r.re[:locked]).max(initial=0.0) < 1e-14 and np.abs(r.re_perp[:locked]).max(initial=0.0) < 1e-14
-    np.testing.assert_allclose(r.re[locked:], full.re[locked:], rtol=1e-12, atol=1e-20)
-    np.testing.assert_allclose(r.re_perp[locked:], full.re_perp[locked:], rtol=1e-10, atol=1e-20)
+    assert np.abs(r.re[lk]).max(initial=0.0) < 1e-14 and np.abs(r.re_perp[lk]).max(initial=0.0) < 1e-14
+    np.testing.assert_allclose(r.re[~lk], full.re[~lk], rtol=1e-12, atol=1e-20)
+    np.testing.assert_allclose(r.re_perp[~lk], full.re_perp[~lk], rtol=1e-10, atol=1e-20)
+    if not lk.any():
+        return
+    # a different locked set gives a different subspace (the set is honoured, not just its size)
+    other = np.roll(lk, 1)
+    if (other != lk).any():
+        ro = mpe.iterate(psi, V, dt, K, grid, box, locked=tuple(np.flatnonzero(other)))
+        assert np.abs(ro.theta - r.theta).max() > 1e-8
 
 
 # ------------------------------------------------------------------ harmonic oscillator
