@@ -178,6 +178,21 @@ mpe_status mpe_small_dense_phases(mpe_plan p, double* us);
  * MPE_ERR_INVALID_ARGUMENT; 0 (the default) propagates every state.  Applies
  * to mpe_iterate only (mpe_step always propagates the whole block). */
 mpe_status mpe_set_locked(mpe_plan p, int32_t locked);
+/* Selective propagation with any set of locked states (Section III: each state
+ * whose variance has reached the bound is left unpropagated, wherever it sits
+ * in the block).  mask: host array of m bytes, nonzero = locked; NULL unlocks
+ * every state.  A leading run (or none) is the same as mpe_set_locked(count).
+ * Otherwise the following mpe_iterate calls form Phi in the order "locked
+ * states ascending, then the others ascending", gathering the rows of psi (one
+ * extra read and write of the block), propagate the unlocked run of it, and
+ * proceed as with mpe_set_locked: the overlaps, Rayleigh-Ritz and R^H do not
+ * depend on the order of Phi's rows, and R^E_j, R^E_perp_j are reported for
+ * state j of the incoming block (0 for the locked ones).  The H Psi reuse of
+ * mpe_set_locked applies alike.  mpe_get_locked reports the number of locked
+ * states.  Copies the mask to the device and synchronises the plan's stream
+ * when the set changes; replaced by the next mpe_set_locked or
+ * mpe_set_locked_states call. */
+mpe_status mpe_set_locked_states(mpe_plan p, const uint8_t* mask);
 /* Whether the following mpe_iterate calls form the overlap M = Psi^T Phi and
  * the variances R^E, R^E_perp (on != 0, the default) or skip them (their
  * outputs are then NaN; eigenvalues and R^H are unaffected).  A driver that

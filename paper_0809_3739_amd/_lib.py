@@ -51,6 +51,7 @@ SIGNATURES = {
     "mpe_forget_cached_h": (C.c_int, [_vp]),
     "mpe_set_states_per_launch": (C.c_int, [_vp, _i32]),
     "mpe_set_locked": (C.c_int, [_vp, _i32]),
+    "mpe_set_locked_states": (C.c_int, [_vp, _vp]),
     "mpe_set_variances": (C.c_int, [_vp, _i32]),
     "mpe_get_locked": (_i32, [_vp]),
     "mpe_set_propagator": (C.c_int, [_vp, _i32]),

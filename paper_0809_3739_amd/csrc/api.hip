@@ -166,7 +166,13 @@ struct mpe_plan_s {
   double tab_dt = -1.0;
   double last_dt = -1.0;
   int states_per_launch = 0;
-  int locked = 0;                    // leading states mpe_iterate leaves unpropagated
+  int locked = 0;                    // states mpe_iterate leaves unpropagated
+  // locked states that are not a leading run (mpe_set_locked_states): Phi is
+  // formed in the order lock_perm (the locked states ascending, then the
+  // others ascending), gathered from psi through the device copy perm
+  bool lock_mapped = false;
+  std::vector<int> lock_perm;
+  int* perm = nullptr;               // device, MAXM entries
   int hfirst = 0;                    // first state whose H phi the next iteration computes
   // launch shapes of the forward [0] and link [1] plane passes (PlaneArgs::persist_mode,
   // work-groups per CU); shape_ver counts changes so a captured graph can notice them
@@ -191,6 +197,7 @@ struct mpe_plan_s {
     const void* psi = nullptr;       // the graph bakes in this state block ...
     int spl = -1;                    // ... and this launch grouping
     int locked = -1;                 // ... and this number of locked states
+    int mapped = -1;                 // ... locked as a leading run (0) or through perm (1)
     int hfirst = -1;                 // ... and this first H state
     int shape = -1;                  // ... and these plane-pass shapes
   } ig[2];
@@ -750,8 +757,25 @@ void host_roots(int L, std::vector<double>& out) {
 mpe_status enqueue_iterate(mpe_plan p, void* psi) {
   // locked states (Section III: only states not yet converged need propagating)
   // enter the overlaps and the rotation unpropagated: Phi_j = Psi_j
-  if (p->locked > 0) HIPCHK(p, launch_copy16(p->phi, psi, (size_t)p->locked * p->N * p->fsz, p->st));
-  mpe_status s = enqueue_propagate(p, psi, p->phi, p->locked);
+  const size_t row = (size_t)p->N * p->fsz;
+  const bool mapped = p->lock_mapped && p->locked > 0;
+  mpe_status s = MPE_OK;
+  if (mapped) {
+    // any locked set: Phi holds the states in the order perm (locked first), so
+    // the propagation covers one contiguous run; the overlaps, the Rayleigh-Ritz
+    // rotation and R^H do not depend on the order of Phi's rows, and the
+    // variances are written back to each state's own entry
+    if (p->hfirst > 0) {
+      // the cached H Psi of the locked states, to the front of hphi (via phi)
+      HIPCHK(p, launch_gather_rows(p->phi, p->hphi, p->perm, p->locked, row, p->st));
+      HIPCHK(p, launch_copy16(p->hphi, p->phi, (size_t)p->locked * row, p->st));
+    }
+    HIPCHK(p, launch_gather_rows(p->phi, psi, p->perm, p->m, row, p->st));
+    s = enqueue_propagate(p, p->phi, p->phi, p->locked);
+  } else {
+    if (p->locked > 0) HIPCHK(p, launch_copy16(p->phi, psi, (size_t)p->locked * row, p->st));
+    s = enqueue_propagate(p, psi, p->phi, p->locked);
+  }
   // H Phi_j = H Psi_j of the locked states is still in hphi from the previous
   // rotation when nothing touched psi since (p->hfirst > 0 only then)
   if (s == MPE_OK) s = run_h(p, p->phi, p->hphi, p->hfirst);
@@ -760,7 +784,8 @@ mpe_status enqueue_iterate(mpe_plan p, void* psi) {
   // S, Hs (upper tiles) and, with the variances, M; contiguous
   if (s == MPE_OK) s = run_gram(p, X, Y, p->variances ? 3 : 2, p->S(), 2);
   if (s == MPE_OK && p->variances) {
-    hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, p->re(), p->reperp(), p->st);
+    hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, mapped ? p->perm : nullptr, p->re(), p->reperp(),
+                                   p->st);
     if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));
   }
   if (s == MPE_OK) s = run_small_dense(p, SD_RR);
@@ -804,6 +829,7 @@ mpe_status capture_iterate(mpe_plan p, void* psi) {
   ig.psi = psi;
   ig.spl = p->states_per_launch;
   ig.locked = p->locked;
+  ig.mapped = p->lock_mapped ? 1 : 0;
   ig.hfirst = p->hfirst;
   ig.shape = p->shape_ver;
   return MPE_OK;
@@ -866,7 +892,7 @@ mpe_status mpe_plan_destroy(mpe_plan p) {
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->gst) (void)hipStreamDestroy(p->gst);
   void* bufs[] = {p->W, p->tailbuf, p->phi, p->hphi, p->V64, p->Vf, p->fac, p->kin, p->hk, p->roots,
-                  p->partials, p->mats, p->rot, p->res, p->ticks, p->fac2, p->kin2, p->rtmp};
+                  p->partials, p->mats, p->rot, p->res, p->ticks, p->fac2, p->kin2, p->rtmp, p->perm};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (p->host_res) (void)hipHostFree(p->host_res);
@@ -960,7 +986,7 @@ mpe_status mpe_plan_create(mpe_plan* out, const int32_t grid[3], const double bo
             alloc(&p->roots, r.size() / 2 * cxs) && alloc((void**)&p->partials, p->partials_bytes) &&
             alloc((void**)&p->mats, 5 * (size_t)p->mp * p->mp * sizeof(double)) &&
             alloc((void**)&p->rot, p->rot_count * 4 * sizeof(double)) && alloc((void**)&p->res, p->res_bytes) &&
-            alloc((void**)&p->ticks, 8 * sizeof(long long));
+            alloc((void**)&p->ticks, 8 * sizeof(long long)) && alloc((void**)&p->perm, MAXM * sizeof(int));
   p->three_pass = !planes_fit;
   p->split_tail = p->three_pass || tail_split(p->dbl, p->nx);
   if (ok && p->split_tail) ok = alloc(&p->tailbuf, (size_t)p->K * m * N * f);
@@ -1113,7 +1139,7 @@ mpe_status mpe_residuals(mpe_plan p, const void* psi, const double* eig, double*
     const void* Y[2] = {p->phi, p->phi};
     s = run_gram(p, X, Y, 2, p->S());   // S = phi phi^T, Hs slot = psi phi^T
     if (s != MPE_OK) return s;
-    HIPCHK(p, launch_variance(p->S(), p->Hs(), p->m, p->mp, p->re(), p->reperp(), p->st));
+    HIPCHK(p, launch_variance(p->S(), p->Hs(), p->m, p->mp, nullptr, p->re(), p->reperp(), p->st));
   }
   // the H psi cache stays valid (psi unchanged)
   HIPCHK(p, hipMemsetAsync(p->status, 0, 4 * sizeof(int), p->st));
@@ -1144,7 +1170,7 @@ mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh
   if (p->use_graph && !p->prof) {
     const mpe_plan_s::IterGraph& ig = p->ig[p->variances ? 1 : 0];
     if (!ig.exec || ig.psi != psi || ig.spl != p->states_per_launch || ig.shape != p->shape_ver ||
-        ig.locked != p->locked || ig.hfirst != p->hfirst) {
+        ig.locked != p->locked || ig.mapped != (p->lock_mapped ? 1 : 0) || ig.hfirst != p->hfirst) {
       s = capture_iterate(p, psi);
       if (s != MPE_OK) return s;
     }
@@ -1244,6 +1270,33 @@ mpe_status mpe_set_locked(mpe_plan p, int32_t locked) {
   if (!p) return MPE_ERR_INVALID_ARGUMENT;
   if (locked < 0 || locked > p->m) return fail(p, MPE_ERR_INVALID_ARGUMENT, "locked must lie in [0, m]");
   p->locked = locked;
+  p->lock_mapped = false;
+  return MPE_OK;
+}
+
+mpe_status mpe_set_locked_states(mpe_plan p, const uint8_t* mask) {
+  if (!p) return MPE_ERR_INVALID_ARGUMENT;
+  int n = 0, lead = 0;
+  if (mask) {
+    for (int j = 0; j < p->m; ++j) n += mask[j] ? 1 : 0;
+    while (lead < p->m && mask[lead]) ++lead;
+  }
+  if (lead == n) return mpe_set_locked(p, n);   // none, or a leading run
+  std::vector<int> perm;
+  perm.reserve(p->m);
+  for (int j = 0; j < p->m; ++j)
+    if (mask[j]) perm.push_back(j);
+  for (int j = 0; j < p->m; ++j)
+    if (!mask[j]) perm.push_back(j);
+  if (!p->lock_mapped || perm != p->lock_perm) {
+    // no replay of a captured iteration is in flight here: mpe_iterate
+    // synchronises before it returns
+    HIPCHK(p, hipMemcpyAsync(p->perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, p->st));
+    HIPCHK(p, hipStreamSynchronize(p->st));
+    p->lock_perm = perm;
+  }
+  p->locked = n;
+  p->lock_mapped = true;
   return MPE_OK;
 }
 
@@ -1836,7 +1889,7 @@ mpe_status enqueue_batch_iterate(mpe_batch b, void* const* psi, hipStream_t st) 
     const void* Y[3] = {p->phi, p->hphi, p->phi};
     mpe_status s = run_gram(p, X, Y, 3, p->S(), 2);
     if (s == MPE_OK) {
-      hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, p->re(), p->reperp(), si);
+      hipError_t e = launch_variance(p->S(), p->Mm(), p->m, p->mp, nullptr, p->re(), p->reperp(), si);
       if (e != hipSuccess) s = fail(p, MPE_ERR_DEVICE, hipGetErrorString(e));
     }
     if (s == MPE_OK) s = run_small_dense(p, SD_RR);

@@ -1077,19 +1077,22 @@ __global__ void fill_kernel(double* p, long n, double v) {
 }
 
 // R^E_j = S_jj - M_jj^2 and R^E_perp_j = S_jj - sum_i M_ij^2 (psi_old orthonormal),
-// with M_ij = (psi_i | phi_j); float64 on mp x mp matrices.
-__global__ void variance_kernel(const double* S, const double* M, int m, int mp, double* re, double* re_perp) {
+// with M_ij = (psi_i | phi_j); float64 on mp x mp matrices.  With a row table,
+// phi_j is the propagated psi_(rows[j]): its variances go to entry rows[j].
+__global__ void variance_kernel(const double* S, const double* M, int m, int mp, const int* rows, double* re,
+                                double* re_perp) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
+  const int r = rows ? rows[j] : j;
   const double sjj = S[(long)j * mp + j];
-  const double mjj = M[(long)j * mp + j];
+  const double mrj = M[(long)r * mp + j];
   double s2 = 0.0;
   for (int i = 0; i < m; ++i) {
     const double v = M[(long)i * mp + j];
     s2 += v * v;
   }
-  re[j] = sjj - mjj * mjj;
-  re_perp[j] = sjj - s2;
+  re[r] = sjj - mrj * mrj;
+  re_perp[r] = sjj - s2;
 }
 
 // Many systems' variances in one launch: work-group j handles job j (m <= 128).
@@ -1364,14 +1367,37 @@ hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t s
   return hipGetLastError();
 }
 
+// Row gather: row i of dst <- row rows[i] of src, i < nrows, rows of row16
+// 16-byte words; work-group (x, i) copies a strided share of row i.  Rows of
+// dst and src must not overlap (the rows are read and written concurrently).
+__global__ void gather_rows16_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                     const int* __restrict__ rows, long row16) {
+  const long i = blockIdx.y;
+  const uint4* s = src + (long)rows[i] * row16;
+  uint4* d = dst + i * row16;
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < row16; k += (long)gridDim.x * blockDim.x) d[k] = s[k];
+}
+
+hipError_t launch_gather_rows(void* dst, const void* src, const int* rows, int nrows, size_t row_bytes,
+                              hipStream_t st) {
+  if (nrows <= 0 || row_bytes == 0) return hipSuccess;
+  if (row_bytes % 16 || nrows > 65535) return hipErrorInvalidValue;
+  const long row16 = (long)(row_bytes / 16);
+  const long bx = std::max<long>(1, std::min<long>(64, (row16 + 255) / 256));
+  hipLaunchKernelGGL(gather_rows16_kernel, dim3((unsigned)bx, (unsigned)nrows), dim3(256), 0, st,
+                     reinterpret_cast<uint4*>(dst), reinterpret_cast<const uint4*>(src), rows, row16);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 
-hipError_t launch_variance(const double* S, const double* M, int m, int mp, double* re, double* re_perp, hipStream_t st) {
-  hipLaunchKernelGGL(variance_kernel, dim3((m + 127) / 128), dim3(128), 0, st, S, M, m, mp, re, re_perp);
+hipError_t launch_variance(const double* S, const double* M, int m, int mp, const int* rows, double* re,
+                           double* re_perp, hipStream_t st) {
+  hipLaunchKernelGGL(variance_kernel, dim3((m + 127) / 128), dim3(128), 0, st, S, M, m, mp, rows, re, re_perp);
   return hipGetLastError();
 }
 

@@ -130,6 +130,12 @@ hipError_t launch_small_dense(const SmallDenseArgs& d, hipStream_t st);
 hipError_t launch_rotate(int is_double, bool with_h, const RotateArgs& r, int nchunks, hipStream_t st);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
 hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st);
-hipError_t launch_variance(const double* S, const double* M, int m, int mp, double* re, double* re_perp, hipStream_t st);
+// row i of dst <- row rows[i] of src (device index table), i < nrows; rows of
+// row_bytes (a multiple of 16); dst and src must not overlap
+hipError_t launch_gather_rows(void* dst, const void* src, const int* rows, int nrows, size_t row_bytes,
+                              hipStream_t st);
+// rows: optional (nullptr = identity) table of the state each column of phi propagates
+hipError_t launch_variance(const double* S, const double* M, int m, int mp, const int* rows, double* re,
+                           double* re_perp, hipStream_t st);
 
 }  // namespace mpe

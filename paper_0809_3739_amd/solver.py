@@ -161,6 +161,18 @@ class Plan:
         iterations (selective propagation; see mpe_set_locked)."""
         self._check(self.lib.mpe_set_locked(self.h, int(locked)))
 
+    def set_locked_states(self, mask):
+        """Leave the states where ``mask`` (m booleans) is true unpropagated in
+        the following iterations, wherever they sit in the block (selective
+        propagation; see mpe_set_locked_states).  None unlocks every state."""
+        if mask is None:
+            self._check(self.lib.mpe_set_locked_states(self.h, None))
+            return
+        mk = np.ascontiguousarray(np.asarray(mask, dtype=bool), dtype=np.uint8)
+        if mk.shape != (self.m,):
+            raise ValueError(f"mask must hold {self.m} entries")
+        self._check(self.lib.mpe_set_locked_states(self.h, mk.ctypes.data_as(C.c_void_p)))
+
     def set_variances(self, on: bool):
         """Form R^E / R^E_perp in the following iterations (default) or skip them
         (NaN outputs, one overlap product fewer); see mpe_set_variances."""
@@ -343,7 +355,8 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
           max_levels: int = 30, orthonormalize_first: bool = True, callback=None,
           stall_window: int | None = None, stall_gain: float = 0.02, accept=None,
           lock_tol: float | None = None, variance_every: int = 1, re_tol: float | None = None,
-          level_stall: int | None = None, stall_below: float | None = None) -> SolveResult:
+          level_stall: int | None = None, stall_below: float | None = None,
+          lock_anywhere: bool = True) -> SolveResult:
     """Iterate with the protocol of Section III until R^H_j < gamma for the
     first ``n_check`` states.
 
@@ -365,9 +378,12 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
 
     With ``lock_tol`` the solve propagates selectively (Section III: only
     states whose variance is still above the bound need propagating): after
-    each iteration the leading run of states (ascending Ritz values, among the
-    first ``n_check``) with R^H_j <= lock_tol is left unpropagated in the next
-    iteration (``Plan.set_locked``).  R^H is evaluated for every state in every
+    each iteration the states (ascending Ritz values, among the first
+    ``n_check``) with R^H_j <= lock_tol are left unpropagated in the next
+    iteration; with ``lock_anywhere`` (the default) every one of those states
+    is, wherever it sits (``Plan.set_locked_states``: a converged state behind
+    an unconverged one is left alone too), else only the leading run of them
+    (``Plan.set_locked``).  R^H is evaluated for every state in every
     iteration, so a locked state whose R^H rises again is released at once;
     locks are dropped when dt changes, and a level only ends on an iteration
     without locks, so its R^E test sees every state propagated.  When every
@@ -439,8 +455,11 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
                     rep = float(np.max(out["re_perp"][:n_check] * np.exp(2.0 * dt * out["eig"][:n_check])))
                 rhm = float(np.max(out["rh"][:n_check]))
                 rh_level.append(rhm)
+                # states this iteration leaves below the lock threshold anywhere among the
+                # checked ones (without lock_anywhere only a leading run of them is locked next)
+                below = 0 if lock_tol is None else int(np.count_nonzero(out["rh"][:n_check] <= lock_tol))
                 hist.append({"dt": dt, "it": total, "re_perp": rep, "rh": rhm, "eig0": float(out["eig"][0]),
-                             "locked": locked, "t": time.perf_counter() - t0})
+                             "locked": locked, "below_lock": below, "t": time.perf_counter() - t0})
                 if callback:
                     callback(hist[-1])
                 if accept is not None:
@@ -462,8 +481,14 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
                 if lock_tol is not None:
                     nl = 0
                     rh = out["rh"]
-                    while nl < n_check and rh[nl] <= lock_tol:
-                        nl += 1
+                    mask = None
+                    if lock_anywhere:
+                        mask = np.zeros(plan.m, dtype=bool)
+                        mask[:n_check] = rh[:n_check] <= lock_tol
+                        nl = int(np.count_nonzero(mask))
+                    else:
+                        while nl < n_check and rh[nl] <= lock_tol:
+                            nl += 1
                     if nl >= n_check:
                         # every checked state is locked, yet max R^H >= gamma (so lock_tol >= gamma):
                         # with nothing left to propagate among them, further iterations at this
@@ -476,7 +501,10 @@ def solve(plan: Plan, psi: torch.Tensor, dt0: float = 0.5, gamma: float = 1e-8, 
                     if it > 0 and rep <= ge:
                         nl = 0   # the level may be done: confirm with every state propagated
                         confirm = True
-                    plan.set_locked(nl)
+                    if mask is not None and nl > 0:
+                        plan.set_locked_states(mask)
+                    else:
+                        plan.set_locked(nl)
                 var_next = variance_every <= 1 or confirm or (it + 1) % variance_every == 0
             if float(np.max(out["rh"][:n_check])) < gamma:
                 return result(out["eig"], out["rh"], level + 1, True)

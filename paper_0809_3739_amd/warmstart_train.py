@@ -179,7 +179,8 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
     random start is i.i.d. N(0, 1) from the geometry's seed.  A ``_lock<f>``
     suffix adds selective propagation: states are locked once their R^H is
     below ``f * gamma`` (f = 1 when omitted) in float32 and below ``gamma / 10``
-    in float64.  ``_g32`` runs the float32 stage's overlaps on float32 MFMA, and
+    in float64; ``_any`` after it locks every such state, not only a leading
+    run of them.  ``_g32`` runs the float32 stage's overlaps on float32 MFMA, and
     a final ``_v<k>`` forms the float32 stage's variances only every k-th
     iteration (10 when omitted).  Every variant starts at the step ``dt0``.
     """
@@ -206,6 +207,8 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
                 name = name[:mv.start()]
             g32 = name.endswith("_g32")
             name = name[:-4] if g32 else name
+            anywhere = name.endswith("_any")
+            name = name[:-4] if anywhere else name
             base, _, lf = name.partition("_lock")
             lock = "_lock" in name
             p32.set_gemm_precision("fp32" if g32 else "fp64")
@@ -220,15 +223,19 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
                 psi = psi.to(torch.float64)
                 q = start_quality(p64, psi)
                 r = solver.solve(p64, psi, dt0=dt0, gamma=gamma, n_check=N_STATES, callback=progress,
-                                 lock_tol=lock64)
+                                 lock_tol=lock64, lock_anywhere=anywhere)
             else:
                 q = start_quality(p32, psi)
                 r = solver.solve_ladder(p32, p64, psi, dt0=dt0, gamma=gamma, n_check=N_STATES, callback=progress,
-                                        lock32=lock32, lock64=lock64, variance_every32=ve)
+                                        lock32=lock32, lock64=lock64, variance_every32=ve, lock_anywhere=anywhere)
             torch.cuda.synchronize()
             secs = time.perf_counter() - t0
+            # propagations of states that sat below the lock threshold but outside the leading run
+            hs = r.history
+            unlocked_below = sum(max(0, a.get("below_lock", 0) - b["locked"]) for a, b in zip(hs, hs[1:]))
             row[var] = {"start_max_rh": q["max_rh"], "first_iteration_max_rh": r.history[0]["rh"],
                         "iterations": r.iterations, "propagations": r.propagations, "seconds": round(secs, 3),
+                        "propagations_below_lock_outside_leading_run": int(unlocked_below),
                         "converged": bool(r.converged), "max_rh": float(np.max(r.rh[:N_STATES])),
                         "stages": r.stages, "eig": [float(e) for e in r.eig[:N_STATES]]}
             log(f"[eval] seed {s} {var}: start R^H {q['max_rh']:.3e}, after one iteration "

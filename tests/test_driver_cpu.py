@@ -16,6 +16,7 @@ class ScriptedPlan:
         self.m, self.n_states = m, n_states
         self.script = list(script)      # per iteration: (rh array, re_perp array)
         self.locked_seen = []
+        self.sets_seen = []
         self.var_seen = []
         self.dts = []
         self._locked = 0
@@ -28,6 +29,13 @@ class ScriptedPlan:
     def set_locked(self, n):
         assert 0 <= n <= self.m
         self._locked = n
+        self.mask_seen_next = None
+
+    def set_locked_states(self, mask):
+        mask = np.asarray(mask, dtype=bool)
+        assert mask.shape == (self.m,)
+        self._locked = int(mask.sum())
+        self.mask_seen_next = tuple(np.flatnonzero(mask))
 
     def set_variances(self, on):
         self._var = bool(on)
@@ -37,6 +45,7 @@ class ScriptedPlan:
 
     def iterate(self, psi, dt):
         self.locked_seen.append(self._locked)
+        self.sets_seen.append(getattr(self, "mask_seen_next", None))
         self.var_seen.append(self._var)
         self.dts.append(dt)
         rh, rep = self.script.pop(0)
@@ -56,11 +65,31 @@ def test_locks_follow_the_leading_converged_run_and_release_at_once():
         ([1e-20] * m, [1.0] * m),                         # all below gamma: converged
     ]
     plan = ScriptedPlan(m, 4, script)
-    r = solver.solve(plan, None, dt0=0.5, gamma=1e-10, lock_tol=1e-11, n_check=4)
+    r = solver.solve(plan, None, dt0=0.5, gamma=1e-10, lock_tol=1e-11, n_check=4, lock_anywhere=False)
     assert r.converged
     assert plan.locked_seen == [0, 2, 3, 1]
     assert r.propagations == 5 + 3 + 2 + 4
     assert plan.locked == 0                               # restored at the end
+
+
+def test_lock_anywhere_locks_every_converged_checked_state():
+    m = 5
+    big, small = 1e-3, 1e-12
+    script = [
+        ([small, big, small, big, small], [1.0] * m),    # states 0, 2 (4 is a guard: not checked)
+        ([small, small, small, big, big], [1.0] * m),    # a leading run 0..2: plain count
+        ([big, small, big, small, small], [1.0] * m),    # 1 and 3, behind an unconverged state 0
+        ([1e-20] * m, [1.0] * m),                         # converged
+    ]
+    plan = ScriptedPlan(m, 4, script)
+    r = solver.solve(plan, None, dt0=0.5, gamma=1e-10, lock_tol=1e-11, n_check=4, lock_anywhere=True)
+    assert r.converged
+    assert plan.locked_seen == [0, 2, 3, 2]
+    assert plan.sets_seen[1] == (0, 2)
+    assert plan.sets_seen[3] == (1, 3)
+    assert r.propagations == 5 + 3 + 2 + 3
+    assert [h["below_lock"] for h in r.history] == [2, 3, 2, 4]
+    assert plan.locked == 0
 
 
 def test_level_ends_only_on_an_unlocked_iteration_and_locks_reset_with_dt():
@@ -74,7 +103,7 @@ def test_level_ends_only_on_an_unlocked_iteration_and_locks_reset_with_dt():
         (lo, [1.0] * m),                       # converged
     ]
     plan = ScriptedPlan(m, 3, script)
-    r = solver.solve(plan, None, dt0=0.4, gamma=1e-10, lock_tol=1e-11)
+    r = solver.solve(plan, None, dt0=0.4, gamma=1e-10, lock_tol=1e-11, lock_anywhere=False)
     assert r.converged
     assert plan.locked_seen == [0, 1, 0, 0, 1]
     assert plan.dts == [0.4, 0.4, 0.4, 0.2, 0.2]
@@ -133,7 +162,7 @@ def test_variances_every_k_iterations_and_for_the_confirming_one():
     far, part, done = ([1e-3] * m, [1.0] * m), ([1e-12, 1e-3, 1e-3], [1.0] * m), ([1e-12, 1e-3, 1e-3], [0.0] * m)
     script = [far, part, part, done, done, ([1e-20] * m, [1.0] * m)]
     plan = ScriptedPlan(m, 3, script)
-    r = solver.solve(plan, None, dt0=0.4, gamma=1e-10, lock_tol=1e-11, variance_every=3)
+    r = solver.solve(plan, None, dt0=0.4, gamma=1e-10, lock_tol=1e-11, variance_every=3, lock_anywhere=False)
     assert r.converged
     # variances in iterations 0 and 3 by the period; 3 meets the R^E test with a lock in force, so 4
     # confirms it unlocked and with variances; the level ends there and the next starts with them
@@ -232,7 +261,8 @@ def test_every_checked_state_locked_above_gamma_ends_the_stage(passes):
         return {"eig": out["eig"], "rh": np.zeros(m)} if (final and passes) else None
 
     plan = ScriptedPlan(m, 2, script)
-    r = solver.solve(plan, None, gamma=1e-10, lock_tol=3e-10, n_check=2, stall_window=20, accept=accept)
+    r = solver.solve(plan, None, gamma=1e-10, lock_tol=3e-10, n_check=2, stall_window=20, accept=accept,
+                     lock_anywhere=False)
     assert r.iterations == 2
     assert calls == [(1, False), (2, False), (2, True)]
     assert plan.locked_seen == [0, 1]

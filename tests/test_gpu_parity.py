@@ -725,6 +725,118 @@ def test_locked_iterate_matches_oracle(P, grid, box, m, order, prec, locks):
             np.testing.assert_allclose(out["rh"], r.rh, rtol=1e-6, atol=1e-14)
 
 
+SET_CASES = [((32, 32, 32), (12.0, 12.0, 12.0), 8, 8, "fp64", "expansion", ((1, 3), (0, 2, 5, 7))),
+             ((128, 128, 8), (16.0, 16.0, 8.0), 4, 4, "fp64", "expansion", ((1, 3),)),   # split tail
+             ((32, 32, 32), (12.0, 12.0, 12.0), 6, 6, "fp32", "expansion", ((1, 4),)),
+             ((32, 32, 32), (12.0, 12.0, 12.0), 6, 4, "fp64", "romberg6", ((0, 2, 3),))]
+
+
+@pytest.mark.parametrize("grid,box,m,order,prec,prop,sets", SET_CASES,
+                         ids=[f"{c[0]}-{c[4]}-{c[5]}" for c in SET_CASES])
+def test_locked_set_iterate_matches_oracle(P, grid, box, m, order, prec, prop, sets):
+    """Selective propagation of any set of states (mpe_set_locked_states): the
+    locked states anywhere in the block are left unpropagated, against the
+    oracle's iteration with the same set; R^E and R^E_perp are compared per
+    incoming state (the plan forms Phi with the locked states first)."""
+    V = toy_potential(grid, box)
+    psi0 = W.random_states(32, m, grid)
+    ref0, _, _ = oracle.cholesky_orthonormalize(rounded(psi0, prec))
+    tol_e, tol_p = (1e-10, 1e-9) if prec == "fp64" else (4e-7, 1.5e-6)
+    for lk in sets:
+        say("locked-set iterate", grid, prec, prop, "m", m, "order", order, "set", lk)
+        plan = P.Plan(grid, box, m, order, prec)
+        plan.set_potential(V)
+        if prop != "expansion":
+            plan.set_propagator(prop)
+        psi = plan.new_states(ref0)
+        mask = np.zeros(m, dtype=bool)
+        mask[list(lk)] = True
+        plan.set_locked_states(mask)
+        assert plan.locked == len(lk)
+        out = plan.iterate(psi, 0.3)
+        r = oracle.iterate(rounded(ref0, prec), V, 0.3, order // 2, grid, box, locked=lk,
+                           romberg6=prop == "romberg6")
+        e = np.max(np.abs(out["eig"] - r.theta) / np.abs(r.theta))
+        Pg = psi.cpu().numpy().astype(np.float64).reshape(m, -1)
+        Pr = r.psi.reshape(m, -1)
+        proj = np.linalg.norm(Pg.T @ (Pg @ Pr.T) - Pr.T) / math.sqrt(m)
+        say(f"  eig rel {e:.2e} proj {proj:.2e}")
+        assert e < tol_e and proj < tol_p
+        if prec == "fp64":
+            assert np.max(np.abs(out["re_perp"][mask])) < 1e-13 and np.max(np.abs(out["re"][mask])) < 1e-13
+            np.testing.assert_allclose(out["re_perp"][~mask], r.re_perp[~mask], rtol=1e-6, atol=1e-14)
+            np.testing.assert_allclose(out["re"][~mask], r.re[~mask], rtol=1e-6, atol=1e-14)
+            np.testing.assert_allclose(out["rh"], r.rh, rtol=1e-6, atol=1e-14)
+        plan.close()
+
+
+def test_locked_set_graph_replay_matches_eager(P):
+    """Locked sets between graph replays: a new set of the same size reuses the
+    captured graph with the new gather table, other sizes and leading runs
+    re-capture it; replay and eager launches agree bitwise, with the H Psi reuse
+    of consecutive iterations in play."""
+    grid, box = (32, 32, 32), (12.0, 12.0, 12.0)
+    say("locked-set graph replay vs eager")
+    V = toy_potential(grid, box)
+    psi0 = W.random_states(9, 8, grid)
+    sets = [(), (1, 3), (2, 4), (0, 1), (0, 5, 6), (2, 4), (1, 2, 3, 4, 5, 6, 7), ()]
+    runs = []
+    for graph in (False, True):
+        plan = P.Plan(grid, box, 8, 6, "fp64")
+        plan.set_potential(V)
+        plan.set_graph(graph)
+        psi = plan.new_states(psi0)
+        plan.orthonormalize(psi)
+        outs = []
+        for lk in sets:
+            mask = np.zeros(8, dtype=bool)
+            mask[list(lk)] = True
+            plan.set_locked_states(mask)
+            assert plan.locked == len(lk)
+            r = plan.iterate(psi, 0.3)
+            outs.append((psi.cpu().numpy().copy(), r["eig"].copy(), r["rh"].copy(), r["re"].copy(),
+                         r["re_perp"].copy()))
+        runs.append(outs)
+        plan.close()
+    for a, b in zip(runs[0], runs[1]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_locked_set_reuses_h_from_the_rotation(P):
+    """With a locked set, the cached H Psi of the locked states (moved to the
+    front with them) serves the next iteration: results match iterations that
+    apply H afresh to float64 rounding."""
+    grid, box = (32, 32, 32), (12.0, 12.0, 12.0)
+    say("locked set reuses H from the rotation")
+    V = toy_potential(grid, box)
+    psi0 = W.random_states(10, 8, grid)
+    sets = [(), (1, 3), (1, 3), (0, 2, 5), (4,), (4, 6)]
+    runs = []
+    for fresh_h in (False, True):
+        plan = P.Plan(grid, box, 8, 6, "fp64")
+        plan.set_potential(V)
+        psi = plan.new_states(psi0)
+        plan.orthonormalize(psi)
+        outs = []
+        for lk in sets:
+            mask = np.zeros(8, dtype=bool)
+            mask[list(lk)] = True
+            plan.set_locked_states(mask)
+            if fresh_h:
+                h = plan.apply_h(psi)   # leaves psi alone, drops the cached H psi
+                del h
+            r = plan.iterate(psi, 0.3)
+            outs.append((psi.cpu().numpy().copy(), r["eig"].copy(), r["rh"].copy()))
+        runs.append(outs)
+        plan.close()
+    for (pa, ea, ra), (pb, eb, rb) in zip(*runs):
+        assert rel_err(ea, eb) < 1e-12
+        assert np.max(np.abs(ra - rb)) < 1e-12 * max(np.max(rb), 1e-30) + 1e-24
+        Pa, Pb = pa.reshape(8, -1), pb.reshape(8, -1)
+        assert np.abs(Pa.T @ (Pa @ Pb.T) - Pb.T).max() < 1e-10
+
+
 def test_locked_graph_replay_matches_eager(P):
     """Changing the number of locked states between graph replays re-captures the
     graph: replay and eager launches agree bitwise over a sequence of locks."""
@@ -824,19 +936,20 @@ def test_solve_with_locking_oscillator(P):
     s = W.harmonic_system(32, 16.0, 10)
     exact = dense.separable_oscillator_levels(32, 16.0, 10)
     res = {}
-    for lock in (None, 1e-11):
-        say("solve oscillator, lock_tol", lock)
+    for lock, anywhere in ((None, False), (1e-11, False), (1e-11, True)):
+        say("solve oscillator, lock_tol", lock, "anywhere", anywhere)
         plan = P.Plan(s.grid, s.box, 10, 4, "fp64")
         plan.set_potential(s.V)
         psi = plan.new_states(W.random_states(1, 10, s.grid))
-        r = P.solve(plan, psi, dt0=0.1, gamma=1e-10, lock_tol=lock)
+        r = P.solve(plan, psi, dt0=0.1, gamma=1e-10, lock_tol=lock, lock_anywhere=anywhere)
         say("  iters", r.iterations, "propagations", r.propagations, "max rel",
             np.max(np.abs(r.eig[:10] - exact) / exact))
         assert r.converged
         assert np.max(np.abs(r.eig[:10] - exact) / exact) < 1e-10
         assert plan.locked == 0
-        res[lock] = r
-    assert res[1e-11].propagations < res[None].propagations
+        res[(lock, anywhere)] = r
+    assert res[(1e-11, False)].propagations < res[(None, False)].propagations
+    assert res[(1e-11, True)].propagations < res[(None, False)].propagations
 
 
 def test_order_study_runs(P):
