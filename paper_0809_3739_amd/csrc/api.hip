@@ -1863,16 +1863,34 @@ mpe_status enqueue_group_h(mpe_batch b, BatchGroup& g, hipStream_t st) {
 }
 
 // All device work of one batched iteration on stream st (plans temporarily enqueue on st).
+// Propagation (and with_h: H) passes of every grid group, ordered after the
+// work on st and before what st receives next.  The groups touch disjoint
+// systems: each runs on a branch stream of its own, so the launches of small
+// grids (few work-groups, latency-bound) overlap those of large ones.
+mpe_status enqueue_groups(mpe_batch b, hipStream_t st, bool with_h) {
+  const int nbr = (int)b->br.size(), ngr = (int)b->groups.size();
+  const int gbr = (nbr > 1 && ngr > 1) ? std::min(nbr, ngr) : 0;
+  if (gbr > 0) {
+    BHIPCHK(b, hipEventRecord(b->ev_fork, st));
+    for (int j = 0; j < gbr; ++j) BHIPCHK(b, hipStreamWaitEvent(b->br[j], b->ev_fork, 0));
+  }
+  for (int gi = 0; gi < ngr; ++gi) {
+    const hipStream_t sg = gbr > 0 ? b->br[gi % gbr] : st;
+    mpe_status s = enqueue_group_step(b, b->groups[gi], sg);
+    if (s == MPE_OK && with_h) s = enqueue_group_h(b, b->groups[gi], sg);
+    if (s != MPE_OK) return s;
+  }
+  for (int j = 0; j < gbr; ++j) {
+    BHIPCHK(b, hipEventRecord(b->ev_join[j], b->br[j]));
+    BHIPCHK(b, hipStreamWaitEvent(st, b->ev_join[j], 0));
+  }
+  return MPE_OK;
+}
+
 mpe_status enqueue_batch_iterate(mpe_batch b, void* const* psi, hipStream_t st) {
   b->launches = 0;
-  for (auto& g : b->groups) {
-    mpe_status s = enqueue_group_step(b, g, st);
-    if (s != MPE_OK) return s;
-  }
-  for (auto& g : b->groups) {
-    mpe_status s = enqueue_group_h(b, g, st);
-    if (s != MPE_OK) return s;
-  }
+  mpe_status gs = enqueue_groups(b, st, true);
+  if (gs != MPE_OK) return gs;
   if (b->batched_la) return enqueue_batch_la(b, st);
   // fork: system i's chain goes to branch i % nbr
   const int nbr = (int)b->br.size();
@@ -2035,11 +2053,9 @@ mpe_status mpe_batch_step(mpe_batch b, void* const* psi, double dt) {
   mpe_status s = upload_descs(b);
   if (s != MPE_OK) return s;
   const int keep = b->launches;   // the count reported is the iteration graph's
-  for (auto& g : b->groups) {
-    s = enqueue_group_step(b, g, b->st);
-    if (s != MPE_OK) return s;
-  }
+  s = enqueue_groups(b, b->st, false);
   b->launches = keep;
+  if (s != MPE_OK) return s;
   BHIPCHK(b, hipStreamSynchronize(b->st));
   return MPE_OK;
 }

@@ -208,6 +208,35 @@ def test_rayleigh_ritz_matches_oracle(P, prec, m, grid):
     assert np.allclose(rh[sep], rh_ref[sep], rtol=1e-6 if prec == "fp64" else 1e-2, atol=1e-20)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_residuals_with_re_match_oracle(P, prec):
+    """mpe_residuals' R^H and R^E (Section III) on an unconverged orthonormal block,
+    elementwise against the oracle: R^E_j = ||T psi_j - mu_j psi_j||^2 with the
+    step size of the last mpe_step."""
+    grid, box = (32, 32, 32), (12.0, 12.0, 12.0)
+    m, order, dt = 6, 6, 0.4
+    say("residuals with R^E", prec)
+    V = toy_potential(grid, box)
+    ref0, _, _ = oracle.cholesky_orthonormalize(rounded(W.random_states(41, m, grid), prec))
+    ref = rounded(ref0, prec)
+    plan = P.Plan(grid, box, m, order, prec)
+    plan.set_potential(V)
+    scratch = plan.new_states(ref)
+    plan.step(scratch, dt)                # sets the step size R^E uses
+    psi = plan.new_states(ref)
+    H = oracle.h_apply(ref, V, grid, box)
+    eig = np.einsum("ij,ij->i", ref.reshape(m, -1), H.reshape(m, -1))   # Rayleigh quotients
+    rh, re = plan.residuals(psi, eig, with_re=True)
+    rh_ref = oracle.residual_h(ref, H, eig)
+    re_ref, _, _ = oracle.residual_e(ref, oracle.mpe_apply(ref, V, dt, order // 2, grid, box))
+    say(f"  R^H rel {np.max(np.abs(rh - rh_ref) / rh_ref):.2e}  R^E rel {np.max(np.abs(re - re_ref) / re_ref):.2e}"
+        f"  R^E range {re_ref.min():.2e}..{re_ref.max():.2e}")
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    np.testing.assert_allclose(rh, rh_ref, rtol=tol)
+    np.testing.assert_allclose(re, re_ref, rtol=tol)
+    plan.close()
+
+
 @pytest.mark.parametrize("m", [1, 2, 3, 17, 63, 64, 65, 127, 128])
 def test_small_dense_edge_sizes(P, m):
     """Block sizes at the edges of the small dense solver's layouts (one state, odd
