@@ -231,9 +231,11 @@ def test_residuals_with_re_match_oracle(P, prec):
     re_ref, _, _ = oracle.residual_e(ref, oracle.mpe_apply(ref, V, dt, order // 2, grid, box))
     say(f"  R^H rel {np.max(np.abs(rh - rh_ref) / rh_ref):.2e}  R^E rel {np.max(np.abs(re - re_ref) / re_ref):.2e}"
         f"  R^E range {re_ref.min():.2e}..{re_ref.max():.2e}")
-    tol = 1e-9 if prec == "fp64" else 1e-4
-    np.testing.assert_allclose(rh, rh_ref, rtol=tol)
-    np.testing.assert_allclose(re, re_ref, rtol=tol)
+    # bars at three to four times the measured errors (float64 3e-15 / 8e-15;
+    # float32 2.5e-7 / 1.3e-6, the float32 transforms and overlaps)
+    tol_h, tol_e = (1e-13, 3e-14) if prec == "fp64" else (1e-6, 5e-6)
+    np.testing.assert_allclose(rh, rh_ref, rtol=tol_h)
+    np.testing.assert_allclose(re, re_ref, rtol=tol_e)
     plan.close()
 
 
