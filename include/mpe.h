@@ -182,14 +182,17 @@ mpe_status mpe_set_locked(mpe_plan p, int32_t locked);
  * whose variance has reached the bound is left unpropagated, wherever it sits
  * in the block).  mask: host array of m bytes, nonzero = locked; NULL unlocks
  * every state.  A leading run (or none) is the same as mpe_set_locked(count).
- * Otherwise the following mpe_iterate calls form Phi in the order "locked
- * states ascending, then the others ascending", gathering the rows of psi (one
- * extra read and write of the block), propagate the unlocked run of it, and
- * proceed as with mpe_set_locked: the overlaps, Rayleigh-Ritz and R^H do not
- * depend on the order of Phi's rows, and R^E_j, R^E_perp_j are reported for
- * state j of the incoming block (0 for the locked ones).  The H Psi reuse of
- * mpe_set_locked applies alike.  mpe_get_locked reports the number of locked
- * states.  Copies the mask to the device and synchronises the plan's stream
+ * Otherwise, with n locked states, the following mpe_iterate calls form Phi
+ * with the locked states in rows 0..n-1 and the others in rows n..m-1 (a
+ * state keeps its own row where that row lies in its part; the locked states
+ * beyond row n-1 trade rows with the unlocked ones before row n), gathering
+ * the rows of psi (one extra read and write of the unlocked states), propagate
+ * rows n..m-1 in place, and proceed as with mpe_set_locked: the overlaps,
+ * Rayleigh-Ritz and R^H do not depend on the order of Phi's rows, and R^E_j,
+ * R^E_perp_j are reported for state j of the incoming block (0 for the locked
+ * ones).  The H Psi reuse of mpe_set_locked applies alike (the cached rows of
+ * the locked states that trade rows move with them).  mpe_get_locked reports
+ * the number of locked states.  Copies the mask to the device and synchronises the plan's stream
  * when the set changes; replaced by the next mpe_set_locked or
  * mpe_set_locked_states call. */
 mpe_status mpe_set_locked_states(mpe_plan p, const uint8_t* mask);

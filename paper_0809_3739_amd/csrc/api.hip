@@ -168,8 +168,9 @@ struct mpe_plan_s {
   int states_per_launch = 0;
   int locked = 0;                    // states mpe_iterate leaves unpropagated
   // locked states that are not a leading run (mpe_set_locked_states): Phi is
-  // formed in the order lock_perm (the locked states ascending, then the
-  // others ascending), gathered from psi through the device copy perm
+  // formed in the order lock_perm (the locked states in rows 0..locked-1, the
+  // others after them, each state in its own row where its part allows),
+  // gathered from psi through the device copy perm
   bool lock_mapped = false;
   std::vector<int> lock_perm;
   int* perm = nullptr;               // device, MAXM entries
@@ -765,11 +766,9 @@ mpe_status enqueue_iterate(mpe_plan p, void* psi) {
     // the propagation covers one contiguous run; the overlaps, the Rayleigh-Ritz
     // rotation and R^H do not depend on the order of Phi's rows, and the
     // variances are written back to each state's own entry
-    if (p->hfirst > 0) {
-      // the cached H Psi of the locked states, to the front of hphi (via phi)
-      HIPCHK(p, launch_gather_rows(p->phi, p->hphi, p->perm, p->locked, row, p->st));
-      HIPCHK(p, launch_copy16(p->hphi, p->phi, (size_t)p->locked * row, p->st));
-    }
+    // the cached H Psi of the locked states outside rows 0..locked-1 moves into
+    // the rows there of unlocked states (whose H the propagation replaces)
+    if (p->hfirst > 0) HIPCHK(p, launch_move_rows(p->hphi, p->perm, p->locked, row, p->st));
     HIPCHK(p, launch_gather_rows(p->phi, psi, p->perm, p->m, row, p->st));
     s = enqueue_propagate(p, p->phi, p->phi, p->locked);
   } else {
@@ -1282,12 +1281,18 @@ mpe_status mpe_set_locked_states(mpe_plan p, const uint8_t* mask) {
     while (lead < p->m && mask[lead]) ++lead;
   }
   if (lead == n) return mpe_set_locked(p, n);   // none, or a leading run
-  std::vector<int> perm;
-  perm.reserve(p->m);
-  for (int j = 0; j < p->m; ++j)
-    if (mask[j]) perm.push_back(j);
-  for (int j = 0; j < p->m; ++j)
-    if (!mask[j]) perm.push_back(j);
+  // rows 0..n-1 take the locked states, rows n..m-1 the others; a state stays
+  // in its own row where that row is in its part, so only the locked states
+  // beyond row n-1 and the unlocked ones before row n trade places (their
+  // rows: destinations below n, sources from n on, as launch_move_rows needs)
+  std::vector<int> lk_hi, un_lo, perm(p->m);
+  for (int j = 0; j < n; ++j)
+    if (!mask[j]) un_lo.push_back(j);
+  for (int j = n; j < p->m; ++j)
+    if (mask[j]) lk_hi.push_back(j);
+  size_t a = 0, c = 0;
+  for (int i = 0; i < n; ++i) perm[i] = mask[i] ? i : lk_hi[a++];
+  for (int i = n; i < p->m; ++i) perm[i] = !mask[i] ? i : un_lo[c++];
   if (!p->lock_mapped || perm != p->lock_perm) {
     // no replay of a captured iteration is in flight here: mpe_iterate
     // synchronises before it returns

@@ -1389,6 +1389,28 @@ hipError_t launch_gather_rows(void* dst, const void* src, const int* rows, int n
   return hipGetLastError();
 }
 
+// In-place row moves: row i of buf <- row rows[i] where rows[i] != i, i < nrows.
+// No row that is moved into may be the source of another move (the moves run
+// concurrently).
+__global__ void move_rows16_kernel(uint4* __restrict__ buf, const int* __restrict__ rows, long row16) {
+  const long i = blockIdx.y;
+  const long r = rows[i];
+  if (r == i) return;
+  const uint4* s = buf + r * row16;
+  uint4* d = buf + i * row16;
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < row16; k += (long)gridDim.x * blockDim.x) d[k] = s[k];
+}
+
+hipError_t launch_move_rows(void* buf, const int* rows, int nrows, size_t row_bytes, hipStream_t st) {
+  if (nrows <= 0 || row_bytes == 0) return hipSuccess;
+  if (row_bytes % 16 || nrows > 65535) return hipErrorInvalidValue;
+  const long row16 = (long)(row_bytes / 16);
+  const long bx = std::max<long>(1, std::min<long>(64, (row16 + 255) / 256));
+  hipLaunchKernelGGL(move_rows16_kernel, dim3((unsigned)bx, (unsigned)nrows), dim3(256), 0, st,
+                     reinterpret_cast<uint4*>(buf), rows, row16);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);

@@ -134,6 +134,9 @@ hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t s
 // row_bytes (a multiple of 16); dst and src must not overlap
 hipError_t launch_gather_rows(void* dst, const void* src, const int* rows, int nrows, size_t row_bytes,
                               hipStream_t st);
+// in place: row i of buf <- row rows[i] for i < nrows with rows[i] != i; no
+// destination row may be the source of another move
+hipError_t launch_move_rows(void* buf, const int* rows, int nrows, size_t row_bytes, hipStream_t st);
 // rows: optional (nullptr = identity) table of the state each column of phi propagates
 hipError_t launch_variance(const double* S, const double* M, int m, int mp, const int* rows, double* re,
                            double* re_perp, hipStream_t st);
