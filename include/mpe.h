@@ -145,12 +145,16 @@ mpe_status mpe_forget_cached_h(mpe_plan p);
  * left unchanged. */
 mpe_status mpe_iterate(mpe_plan p, void* psi, double dt, double* eig, double* rh, double* re, double* re_perp);
 
-/* Graph replay of mpe_iterate (on by default).  The first call for a given
- * psi array captures the iteration's launches into a hipGraph on a private
- * stream ordered after the plan's stream; later calls with the same psi and
- * launch grouping replay it (dt enters through tables rebuilt outside the
- * graph).  Off: every launch is enqueued eagerly. Kernel timing (below) uses
- * the eager path. */
+/* Graph replay of mpe_iterate (off by default).  On: the first call for a
+ * given psi array captures the iteration's launches into a hipGraph on a
+ * private stream ordered after the plan's stream; later calls with the same
+ * psi, launch grouping and lock setting replay it (dt enters through tables
+ * rebuilt outside the graph).  Off: every launch is enqueued eagerly on the
+ * plan's stream.  Eager is the default because it measured as fast or faster
+ * on MI355X at every size tried (32^3 x 8 states: 0.37 against 0.39 ms per
+ * iteration; 128^3 x 125 float32: 32.1 against 32.6 ms): the GPU work of an
+ * iteration hides the enqueueing, and a change of the locked states needs no
+ * re-capture.  Kernel timing (below) uses the eager path. */
 mpe_status mpe_set_graph(mpe_plan p, int32_t on);
 
 /* Jacobi sweeps used by the last successful Rayleigh-Ritz solve of

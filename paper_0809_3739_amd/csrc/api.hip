@@ -189,7 +189,7 @@ struct mpe_plan_s {
   const void* rr_cache_psi = nullptr;   // H psi cached in hphi for this psi
 
   // graph replay of the fused iteration
-  bool use_graph = true;
+  bool use_graph = false;      // replay a captured iteration (mpe_set_graph); eager launches by default
   hipStream_t gst = nullptr;         // private stream for capture and replay
   // one captured iteration per variance setting (slot = variances on)
   struct IterGraph {
