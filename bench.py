@@ -89,7 +89,9 @@ def headline_solve(seed: int = 10000, n_guard: int = 8, dt0: float = 1.5) -> dic
 
     Every solve starts at the step dt0 = 1.5: the largest of 0.5, 0.75, 1, 1.5, 2, 3 at which the order-12
     iteration's fixed point still lies below the residual target (its error grows as dt^12; at 2 the
-    float32 stage stalls near 4e-8), so the fewest iterations reach it."""
+    float32 stage stalls near 4e-8), so the fewest iterations reach it.  The float32 stage hands over to
+    float64 without the periodic float64 checks of its block (one check once every checked state is
+    locked): on eight held-out seeds none of those checks ended a solve, and they cost 4 % of its time."""
     import numpy as np
     from paper_0809_3739_amd import warmstart_train as T
     from paper_0809_3739_amd.warmstart import WarmStartNet
@@ -97,7 +99,7 @@ def headline_solve(seed: int = 10000, n_guard: int = 8, dt0: float = 1.5) -> dic
         meta = json.loads(str(z["meta"]))
     net = WarmStartNet(grid=T.COARSE, n_out=int(meta.get("n_out", T.N_STATES)), max_batch=1)
     T.load_weights(net)
-    variants = ("learned_ladder_lock3_any_g32", "random_fp64_lock_any", "random_fp64")
+    variants = ("learned_ladder_lock3_any_c0_g32", "random_fp64_lock_any", "random_fp64")
     row = T.compare_starts(net, [seed], grid=128, n_guard=n_guard, gamma=1e-8, variants=variants,
                            log=lambda m: print(m, file=sys.stderr, flush=True), dt0=dt0)[0]
     net.close()
@@ -114,9 +116,9 @@ def headline_solve(seed: int = 10000, n_guard: int = 8, dt0: float = 1.5) -> dic
     ref = e["random_fp64"]
     out["max_abs_eig_diff_vs_random_fp64"] = {v: float(np.max(np.abs(e[v] - ref))) for v in variants[:2]}
     out["speedup_learned_fp32_vs_random_fp64"] = round(row["random_fp64"]["seconds"] /
-                                                       row["learned_ladder_lock3_any_g32"]["seconds"], 3)
+                                                       row["learned_ladder_lock3_any_c0_g32"]["seconds"], 3)
     out["speedup_learned_fp32_vs_random_fp64_lock"] = round(row["random_fp64_lock_any"]["seconds"] /
-                                                            row["learned_ladder_lock3_any_g32"]["seconds"], 3)
+                                                            row["learned_ladder_lock3_any_c0_g32"]["seconds"], 3)
     return out
 
 

@@ -180,7 +180,9 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
     suffix adds selective propagation: states are locked once their R^H is
     below ``f * gamma`` (f = 1 when omitted) in float32 and below ``gamma / 10``
     in float64; ``_any`` after it locks every such state, not only a leading
-    run of them.  ``_g32`` runs the float32 stage's overlaps on float32 MFMA, and
+    run of them; ``_c<x>`` after that sets the ladder's ``check_below`` (the
+    float64 checks of the float32 stage start below x * gamma; 10 when omitted,
+    0 leaves only the check once every state is locked).  ``_g32`` runs the float32 stage's overlaps on float32 MFMA, and
     a final ``_v<k>`` forms the float32 stage's variances only every k-th
     iteration (10 when omitted).  Every variant starts at the step ``dt0``.
     """
@@ -207,6 +209,11 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
                 name = name[:mv.start()]
             g32 = name.endswith("_g32")
             name = name[:-4] if g32 else name
+            cb = 10.0
+            mc = re.search(r"_c(\d+(?:\.\d+)?)$", name)
+            if mc:
+                cb = float(mc.group(1))
+                name = name[:mc.start()]
             anywhere = name.endswith("_any")
             name = name[:-4] if anywhere else name
             base, _, lf = name.partition("_lock")
@@ -227,7 +234,8 @@ def compare_starts(net: WarmStartNet, seeds, grid: int = 128, n_guard: int = 5, 
             else:
                 q = start_quality(p32, psi)
                 r = solver.solve_ladder(p32, p64, psi, dt0=dt0, gamma=gamma, n_check=N_STATES, callback=progress,
-                                        lock32=lock32, lock64=lock64, variance_every32=ve, lock_anywhere=anywhere)
+                                        lock32=lock32, lock64=lock64, variance_every32=ve, lock_anywhere=anywhere,
+                                        check_below=cb)
             torch.cuda.synchronize()
             secs = time.perf_counter() - t0
             # propagations of states that sat below the lock threshold but outside the leading run
