@@ -268,3 +268,29 @@ def test_every_checked_state_locked_above_gamma_ends_the_stage(passes):
     assert plan.locked_seen == [0, 1]
     assert (r.converged, r.stalled) == ((True, False) if passes else (False, True))
     assert plan.locked == 0
+
+
+def test_every_checked_state_locked_anywhere_ends_the_stage():
+    """With converged states locked wherever they sit, the stage also ends once
+    every checked state is locked, reached through a non-leading set first."""
+    m = 4
+    script = [
+        ([5e-4, 2e-10, 1e-3, 2e-10], [1.0] * m),       # checked states 1 (and 3, a guard) below lock_tol
+        ([5e-4, 2e-10, 2.5e-10, 1e-3], [1.0] * m),     # states 1, 2: a non-leading set of two
+        ([2e-10, 2e-10, 2.5e-10, 1e-3], [1.0] * m),    # all three checked states locked, max 2.5e-10 > gamma
+    ] + [([2e-10, 2e-10, 2.5e-10, 1e-3], [1.0] * m)] * 30
+    calls = []
+
+    def accept(out, it, final=False):
+        calls.append((it, final))
+        return None
+
+    plan = ScriptedPlan(m, 3, script)
+    r = solver.solve(plan, None, gamma=1e-10, lock_tol=3e-10, n_check=3, stall_window=20, accept=accept)
+    assert r.iterations == 3
+    assert calls == [(1, False), (2, False), (3, False), (3, True)]
+    assert plan.locked_seen == [0, 1, 2]
+    assert plan.sets_seen[1] == (1,) and plan.sets_seen[2] == (1, 2)
+    assert (r.converged, r.stalled) == (False, True)
+    assert r.propagations == 4 + 3 + 2
+    assert plan.locked == 0
