@@ -109,3 +109,14 @@ def test_warm_start_net_rejects_bad_shapes_before_device_work(lib):
     assert lib.wsn_destroy(None) == 1
     assert lib.wsn_last_error(None) == b"null network"
     assert lib.wsn_upsample_periodic(None, 1, 4, 2, None, None) == 1
+
+
+def test_null_plan_setters_fail_before_device_work(lib):
+    """Setters on a null plan return MPE_ERR_INVALID_ARGUMENT without touching a device."""
+    mask = (C.c_uint8 * 4)(0, 1, 0, 1)
+    assert lib.mpe_set_locked(None, 1) == 1
+    assert lib.mpe_set_locked_states(None, C.cast(mask, C.c_void_p)) == 1
+    assert lib.mpe_set_locked_states(None, None) == 1
+    assert lib.mpe_get_locked(None) == -1
+    assert lib.mpe_set_graph(None, 1) == 1
+    assert lib.mpe_set_variances(None, 1) == 1
